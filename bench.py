@@ -1,0 +1,226 @@
+"""Benchmark of the NUFFT DDI path on one MI355X.
+
+Headline: DDI evaluations per second at 128^3 in FP64 (workload c2_128: seeded Gaussian-mixture
+density on [-12,12)^3, random unit dipole axis, spherical quadrature 96 x 48 x 96, NUFFT
+tolerance 1e-13).  One step = one ddi_apply (deconvolve/pad + FFT, interpolation and
+weighting, spread, FFT + truncate/deconvolve).  The same input is also run in the mixed
+form (FP32 grids, Kahan spread, FP64 tables) and as forward+adjoint pairs.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+METRIC = "DDI evals/s at 128³ (FP64 vs mixed, rel L∞ ≤1e-6); fwd+adjoint ms"
+
+
+def stage_model(plan, real_bytes, cplx_bytes):
+    """Algorithmic HBM bytes and flops of each stage of one apply.
+
+    FFT passes: the active part of each line is read and written once.  Interpolation:
+    the fine grid is read once, plus node records and node values.  Spread: the fine grid
+    is written once, plus node records, node values and the tile lists.  Flops of
+    interpolation/spread: 4 per (node, grid point) pair (a real weight times a complex
+    value accumulated), w^d pairs per node; of an FFT pass: 5 n log2 n per line.
+    """
+    N = [1] * (3 - plan.dim) + list(plan.shape)
+    nf = list(plan.info["n_fine"])
+    w = plan.info["width"]
+    M = plan.m_eff
+    d = plan.dim
+    rec = 16 + 3 * 16 * real_bytes
+    c = cplx_bytes
+
+    def fftf(n, lines):
+        return 5.0 * n * math.log2(n) * lines if n > 1 else 0.0
+
+    st = {}
+    st["fft_last_pad"] = (N[0] * N[1] * N[2] * real_bytes + N[0] * N[1] * nf[2] * c, fftf(nf[2], N[0] * N[1]))
+    st["fft_axis1_t2"] = (N[0] * N[1] * nf[2] * c + N[0] * nf[1] * nf[2] * c, fftf(nf[1], N[0] * nf[2]))
+    st["fft_axis0_t2"] = ((N[0] * nf[1] * nf[2] * c + nf[0] * nf[1] * nf[2] * c) if nf[0] > 1 else 0,
+                          fftf(nf[0], nf[1] * nf[2]))
+    st["interp"] = (nf[0] * nf[1] * nf[2] * c + M * (rec + c + 8), 4.0 * M * w ** d)
+    st["spread"] = (nf[0] * nf[1] * nf[2] * c + M * (rec + c) + 4 * plan.info["spread_entries"], 4.0 * M * w ** d)
+    st["spread_reduce"] = (0.0, 0.0)
+    st["fft_axis0_t1"] = st["fft_axis0_t2"]
+    st["fft_axis1_t1"] = st["fft_axis1_t2"]
+    st["fft_last_trunc"] = st["fft_last_pad"]
+    return st
+
+
+def roofline_of(stage, ms, model, fp_peak_tflops):
+    b, f = model[stage]
+    gbs = b / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    tfl = f / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+    fr_h = gbs / HBM_PEAK_GBS
+    fr_f = tfl / fp_peak_tflops
+    if stage in ("interp", "spread"):
+        return {"bound": "alu", "achieved": round(tfl, 3), "peak": fp_peak_tflops, "unit": "TFLOP/s",
+                "frac": round(fr_f, 4), "traffic": None, "kernel": stage, "kernel_ms": round(ms, 4),
+                "hbm_GBs_algorithmic": round(gbs, 1), "hbm_frac": round(fr_h, 4),
+                "algorithmic_flops": f, "algorithmic_bytes": b}
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(fr_h, 4), "traffic": None, "kernel": stage, "kernel_ms": round(ms, 4),
+            "algorithmic_bytes": b, "algorithmic_flops": f}
+
+
+def time_steps(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        fn()
+    end.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / steps
+
+
+def cpu_baseline(wl, rho, dip, M_eff, target_s):
+    """The oracle on a bounded sample: the full grid and a seeded random subset of nodes
+    (type-2 sums to those nodes, type-1 sums back), scaled to evals/s by M_eff / M_sample."""
+    import numpy as np
+    from oracle import ddi_oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("user_api") == "blas"] or [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    prob = O.DDIProblem(dim=wl["dim"], n=wl["n"], L=wl["L"], dip_n=tuple(dip), n_rad=wl["quad"][0],
+                        n_pol=wl["quad"][1], n_azi=wl["quad"][2])
+    quad, c = O.ddi_nodes(prob)
+    rng = np.random.default_rng(123)
+
+    def run(m):
+        sel = np.sort(rng.choice(quad.k.shape[0], size=m, replace=False))
+        t0 = time.perf_counter()
+        rh = O.rhohat(rho, prob, quad.k[sel])
+        O.nodes_to_grid(c[sel] * rh, prob, quad.k[sel])
+        return time.perf_counter() - t0
+
+    m0 = 512
+    t0 = run(m0)
+    m = int(min(quad.k.shape[0], max(m0, m0 * target_s / max(t0, 1e-3))))
+    t = run(m)
+    return {"value": round((m / quad.k.shape[0]) / t, 6), "unit": "evals/s", "cores": int(cores),
+            "kind": "oracle",
+            "sample": f"c2_128 full 128^3 grid x {m} of {quad.k.shape[0]} quadrature nodes "
+                      f"(seeded random subset), direct type-2 + type-1 sums in FP64, {t:.1f} s; "
+                      f"evals/s = (sample/M_eff)/time"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--profile-reps", type=int, default=10)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (see the sharding notes); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1504_02897_amd import inputs as I
+    from paper_1504_02897_amd.ddi import DDIPlan
+
+    torch.cuda.set_device(0)
+    name = "c2_128"
+    wl = I.WORKLOADS[name]
+    data = I.mixture_workload(name, seed=args.seed)
+    rho64 = torch.from_numpy(data["rho"]).cuda()
+    dip = tuple(float(v) for v in data["dip_n"])
+    out = {}
+
+    print(f"[bench] plan fp64 {name}", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    p64 = DDIPlan(3, wl["n"], wl["L"], dip_n=dip, quad=wl["quad"], tol=wl["tol"], prec="fp64")
+    plan_s = time.perf_counter() - t0
+    phi64 = torch.empty_like(rho64)
+    adj64 = torch.empty_like(rho64)
+    ms64 = time_steps(lambda: p64.apply(rho64, out=phi64), args.steps, args.warmup, torch)
+    print(f"[bench] fp64 {ms64:.3f} ms/eval", file=sys.stderr, flush=True)
+    fa64 = time_steps(lambda: (p64.apply(rho64, out=phi64), p64.apply_adjoint(phi64, out=adj64)),
+                      max(1, args.steps // 2), 2, torch)
+    stages64 = p64.profile(rho64, reps=args.profile_reps)
+    phi_ref = p64.apply(rho64).cpu().numpy()
+
+    print(f"[bench] plan mixed {name}", file=sys.stderr, flush=True)
+    p32 = DDIPlan(3, wl["n"], wl["L"], dip_n=dip, quad=wl["quad"], tol=1e-7, prec="mixed")
+    rho32 = rho64.float()
+    phi32 = torch.empty_like(rho32)
+    adj32 = torch.empty_like(rho32)
+    ms32 = time_steps(lambda: p32.apply(rho32, out=phi32), args.steps, args.warmup, torch)
+    fa32 = time_steps(lambda: (p32.apply(rho32, out=phi32), p32.apply_adjoint(phi32, out=adj32)),
+                      max(1, args.steps // 2), 2, torch)
+    stages32 = p32.profile(rho32, reps=args.profile_reps)
+    phim = p32.apply(rho32).double().cpu().numpy()
+    err_mixed = float(np.max(np.abs(phim - phi_ref)) / np.max(np.abs(phi_ref)))
+    print(f"[bench] mixed {ms32:.3f} ms/eval, rel Linf vs fp64 {err_mixed:.2e}", file=sys.stderr, flush=True)
+
+    model64 = stage_model(p64, 8, 16)
+    dom = max(stages64, key=stages64.get)
+    roof = roofline_of(dom, stages64[dom], model64, FP64_PEAK_TFLOPS)
+    roof["stages_ms"] = {k: round(v, 4) for k, v in stages64.items()}
+    model32 = stage_model(p32, 4, 8)
+    dom32 = max(stages32, key=stages32.get)
+    roof32 = roofline_of(dom32, stages32[dom32], model32, FP32_PEAK_TFLOPS)
+    roof32["stages_ms"] = {k: round(v, 4) for k, v in stages32.items()}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle, bounded sample)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(wl, data["rho"], dip, p64.m_eff, args.cpu_seconds)
+
+    line = {
+        "metric": METRIC,
+        "value": round(1000.0 / ms64, 3),
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms64, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "c2_128: 3D DDI, 128^3 on [-12,12)^3, seeded Gaussian-mixture density "
+                               f"(seed {args.seed}), random unit dipole axis, quadrature 96x48x96, tol 1e-13",
+                   "m_eff": p64.m_eff, "n_fine": list(p64.info["n_fine"]), "kernel_width": p64.info["width"],
+                   "plan_s": round(plan_s, 2)},
+        "fwd_adj_ms": round(fa64, 4),
+        "mixed": {"value": round(1000.0 / ms32, 3), "unit": "evals/s", "ms_per_step": round(ms32, 4),
+                  "fwd_adj_ms": round(fa32, 4), "rel_linf_vs_fp64": err_mixed,
+                  "kernel_width": p32.info["width"], "roofline": roof32},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

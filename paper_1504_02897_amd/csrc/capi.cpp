@@ -1,0 +1,351 @@
+// C ABI of libddi (declared in include/ddi.h): plan construction, device
+// uploads, argument checks and dispatch on the precision.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "ddi_internal.h"
+
+struct ddi_plan_s {
+  ddi::DevicePlan P;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+ddi_status fail(ddi_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+ddi_status hip_fail(hipError_t e, const char* what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return e == hipErrorOutOfMemory ? DDI_ENOMEM : DDI_EDEVICE;
+}
+
+#define HIP_TRY(call, what)                        \
+  do {                                             \
+    hipError_t e_ = (call);                        \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+template <typename X>
+hipError_t upload(X** dst, const X* src, size_t count, hipStream_t s, int64_t& bytes) {
+  if (count == 0) { *dst = nullptr; return hipSuccess; }
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), count * sizeof(X));
+  if (e != hipSuccess) return e;
+  bytes += static_cast<int64_t>(count * sizeof(X));
+  return hipMemcpyAsync(*dst, src, count * sizeof(X), hipMemcpyHostToDevice, s);
+}
+
+void free_plan(ddi::DevicePlan& P) {
+  void* ptrs[] = {P.nodes, P.c_scaled, P.deconv[0], P.deconv[1], P.deconv[2], P.list, P.items, P.reduces,
+                  P.fine, P.gnodes, P.partial, P.gpe_rho, P.gpe_phi, P.gpe_phit, P.gpe_c1, P.gpe_c2, P.gpe_red};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  for (void* p : P.twiddles)
+    if (p) (void)hipFree(p);
+}
+
+template <typename T>
+ddi_status build_device(ddi::DevicePlan& P, hipStream_t s, std::vector<ddi::NodeRec<T>>& recs,
+                        std::vector<std::vector<ddi::Complex<T>>>& tws) {
+  const ddi::HostTables& H = P.H;
+  int64_t& bytes = P.workspace_bytes;
+  recs.resize(H.M);
+  for (int64_t q = 0; q < H.M; ++q) {
+    ddi::NodeRec<T>& r = recs[q];
+    std::memset(&r, 0, sizeof(r));
+    for (int a = 0; a < 3; ++a) {
+      r.l0[a] = H.l0[3 * q + a];
+      for (int i = 0; i < ddi::kWMax; ++i) r.w[a][i] = static_cast<T>(H.wts[(q * 3 + a) * ddi::kWMax + i]);
+    }
+  }
+  ddi::NodeRec<T>* dn = nullptr;
+  HIP_TRY(upload(&dn, recs.data(), recs.size(), s, bytes), "upload node table");
+  P.nodes = dn;
+  std::vector<double> cs(H.M);
+  for (int64_t q = 0; q < H.M; ++q) cs[q] = H.c[q] * H.cell;
+  HIP_TRY(upload(&P.c_scaled, cs.data(), cs.size(), s, bytes), "upload weights");
+  for (int a = 0; a < 3; ++a)
+    HIP_TRY(upload(&P.deconv[a], H.deconv[a].data(), H.deconv[a].size(), s, bytes), "upload deconvolution");
+  HIP_TRY(upload(&P.list, H.list.data(), H.list.size(), s, bytes), "upload spread lists");
+  HIP_TRY(upload(&P.items, H.items.data(), H.items.size(), s, bytes), "upload spread items");
+  HIP_TRY(upload(&P.reduces, H.reduces.data(), H.reduces.size(), s, bytes), "upload spread reduces");
+  // twiddles for every FFT length used: fine grid sizes and the unpadded sizes
+  tws.assign(11, {});
+  for (int a = 0; a < 3; ++a) {
+    for (int n : {H.nf[a], H.N[a]}) {
+      if (n < 2) continue;
+      int l = 0;
+      while ((1 << l) < n) ++l;
+      if (P.twiddles[l]) continue;
+      std::vector<double> t = ddi::twiddle_table(n);
+      tws[l].resize(n);
+      for (int k = 0; k < n; ++k) tws[l][k] = {static_cast<T>(t[2 * k]), static_cast<T>(t[2 * k + 1])};
+      ddi::Complex<T>* d = nullptr;
+      HIP_TRY(upload(&d, tws[l].data(), tws[l].size(), s, bytes), "upload twiddles");
+      P.twiddles[l] = d;
+    }
+  }
+  const int64_t nfine = static_cast<int64_t>(H.nf[0]) * H.nf[1] * H.nf[2];
+  HIP_TRY(hipMalloc(&P.fine, nfine * sizeof(ddi::Complex<T>)), "allocate fine grid");
+  bytes += nfine * static_cast<int64_t>(sizeof(ddi::Complex<T>));
+  HIP_TRY(hipMalloc(&P.gnodes, H.M * sizeof(ddi::Complex<T>)), "allocate node values");
+  bytes += H.M * static_cast<int64_t>(sizeof(ddi::Complex<T>));
+  if (H.nslots > 0) {
+    const int64_t pbytes = static_cast<int64_t>(H.nslots) * 64 * ddi::kTileZ * sizeof(ddi::Complex<T>);
+    HIP_TRY(hipMalloc(&P.partial, pbytes), "allocate spread partial tiles");
+    bytes += pbytes;
+  }
+  return DDI_OK;
+}
+
+template <typename T>
+ddi_status ensure_gpe(ddi::DevicePlan& P) {
+  if (P.gpe_rho) return DDI_OK;
+  const int64_t n = static_cast<int64_t>(P.H.N[0]) * P.H.N[1] * P.H.N[2];
+  P.gpe_red_blocks = ddi::gpe_reduction_blocks<T>(P);
+  HIP_TRY(hipMalloc(&P.gpe_rho, n * sizeof(T)), "allocate GPE workspace");
+  HIP_TRY(hipMalloc(&P.gpe_phi, n * sizeof(T)), "allocate GPE workspace");
+  HIP_TRY(hipMalloc(&P.gpe_phit, n * sizeof(T)), "allocate GPE workspace");
+  HIP_TRY(hipMalloc(&P.gpe_c1, n * sizeof(ddi::Complex<T>)), "allocate GPE workspace");
+  HIP_TRY(hipMalloc(&P.gpe_c2, n * sizeof(ddi::Complex<T>)), "allocate GPE workspace");
+  HIP_TRY(hipMalloc(reinterpret_cast<void**>(&P.gpe_red), (8 * P.gpe_red_blocks + 16) * sizeof(double)),
+          "allocate GPE workspace");
+  P.workspace_bytes += n * (3 * sizeof(T) + 2 * sizeof(ddi::Complex<T>));
+  return DDI_OK;
+}
+
+ddi_status check_plan(ddi_plan_t plan) {
+  if (!plan) return fail(DDI_EINVAL, "plan is NULL");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(DDI_EDEVICE, "hipGetDevice failed");
+  if (dev != plan->P.device) return fail(DDI_EINVAL, "the current device differs from the plan's device");
+  return DDI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ddi_last_error(void) { return g_err.c_str(); }
+
+ddi_status ddi_plan(const ddi_params* params, void* stream, ddi_plan_t* out) {
+  g_err.clear();
+  if (!out) return fail(DDI_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!params) return fail(DDI_EINVAL, "params is NULL");
+  ddi_plan_s* plan = new (std::nothrow) ddi_plan_s();
+  if (!plan) return fail(DDI_ENOMEM, "host allocation failed");
+  ddi::DevicePlan& P = plan->P;
+  int st = DDI_OK;
+  std::string msg;
+  try {
+    msg = ddi::build_tables(*params, P.H, &st);
+  } catch (const std::bad_alloc&) {
+    delete plan;
+    return fail(DDI_ENOMEM, "host allocation failed while building plan tables");
+  } catch (...) {
+    delete plan;
+    return fail(DDI_EINTERNAL, "unexpected error while building plan tables");
+  }
+  if (st != DDI_OK) {
+    delete plan;
+    return fail(static_cast<ddi_status>(st), msg);
+  }
+  P.mixed = params->prec == DDI_MIXED;
+  if (hipGetDevice(&P.device) != hipSuccess) {
+    delete plan;
+    return fail(DDI_EDEVICE, "no HIP device");
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  ddi_status ds;
+  std::vector<ddi::NodeRec<double>> rd;
+  std::vector<ddi::NodeRec<float>> rf;
+  std::vector<std::vector<ddi::Complex<double>>> td;
+  std::vector<std::vector<ddi::Complex<float>>> tf;
+  try {
+    ds = P.mixed ? build_device<float>(P, s, rf, tf) : build_device<double>(P, s, rd, td);
+  } catch (const std::bad_alloc&) {
+    ds = fail(DDI_ENOMEM, "host allocation failed while uploading plan tables");
+  }
+  if (ds == DDI_OK) {
+    hipError_t e = hipStreamSynchronize(s);   // host staging buffers die at return
+    if (e != hipSuccess) ds = hip_fail(e, "plan upload");
+  }
+  if (ds != DDI_OK) {
+    (void)hipStreamSynchronize(s);
+    free_plan(P);
+    delete plan;
+    return ds;
+  }
+  *out = plan;
+  return DDI_OK;
+}
+
+void ddi_destroy(ddi_plan_t plan) {
+  if (!plan) return;
+  free_plan(plan->P);
+  delete plan;
+}
+
+ddi_status ddi_plan_info(ddi_plan_t plan, ddi_plan_info_t* info) {
+  if (!plan || !info) return fail(DDI_EINVAL, "plan or info is NULL");
+  const ddi::HostTables& H = plan->P.H;
+  info->m_eff = H.M;
+  info->m_nominal = H.m_nominal;
+  for (int a = 0; a < 3; ++a) info->n_fine[a] = H.nf[a];
+  info->width = H.w;
+  info->es_beta = H.es_beta;
+  info->kmax = H.kmax;
+  info->spread_items = static_cast<int64_t>(H.items.size());
+  info->spread_entries = static_cast<int64_t>(H.list.size());
+  info->workspace_bytes = plan->P.workspace_bytes;
+  return DDI_OK;
+}
+
+ddi_status ddi_plan_nodes(ddi_plan_t plan, int32_t* index_host, double* k_host, double* c_host) {
+  if (!plan) return fail(DDI_EINVAL, "plan is NULL");
+  const ddi::HostTables& H = plan->P.H;
+  if (index_host) std::memcpy(index_host, H.index.data(), H.index.size() * sizeof(int32_t));
+  if (k_host) std::memcpy(k_host, H.k.data(), H.k.size() * sizeof(double));
+  if (c_host) std::memcpy(c_host, H.c.data(), H.c.size() * sizeof(double));
+  return DDI_OK;
+}
+
+ddi_status ddi_apply(ddi_plan_t plan, const void* rho_dev, void* phi_dev, void* stream) {
+  ddi_status st = check_plan(plan);
+  if (st != DDI_OK) return st;
+  if (!rho_dev || !phi_dev) return fail(DDI_EINVAL, "NULL buffer");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  ddi::DevicePlan& P = plan->P;
+  hipError_t e = P.mixed ? ddi::run_apply<float>(P, static_cast<const float*>(rho_dev), static_cast<float*>(phi_dev), +1, s, nullptr)
+                         : ddi::run_apply<double>(P, static_cast<const double*>(rho_dev), static_cast<double*>(phi_dev), +1, s, nullptr);
+  if (e != hipSuccess) return hip_fail(e, "ddi_apply launch");
+  return DDI_OK;
+}
+
+ddi_status ddi_apply_adjoint(ddi_plan_t plan, const void* phibar_dev, void* rhobar_dev, void* stream) {
+  ddi_status st = check_plan(plan);
+  if (st != DDI_OK) return st;
+  if (!phibar_dev || !rhobar_dev) return fail(DDI_EINVAL, "NULL buffer");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  ddi::DevicePlan& P = plan->P;
+  hipError_t e = P.mixed ? ddi::run_apply<float>(P, static_cast<const float*>(phibar_dev), static_cast<float*>(rhobar_dev), -1, s, nullptr)
+                         : ddi::run_apply<double>(P, static_cast<const double*>(phibar_dev), static_cast<double*>(rhobar_dev), -1, s, nullptr);
+  if (e != hipSuccess) return hip_fail(e, "ddi_apply_adjoint launch");
+  return DDI_OK;
+}
+
+ddi_status ddi_profile_apply(ddi_plan_t plan, const void* in_dev, void* out_dev, int32_t sign, int32_t reps,
+                             double* stage_ms, void* stream) {
+  ddi_status st = check_plan(plan);
+  if (st != DDI_OK) return st;
+  if (!in_dev || !out_dev || !stage_ms) return fail(DDI_EINVAL, "NULL argument");
+  if (sign != 1 && sign != -1) return fail(DDI_EINVAL, "sign must be +1 or -1");
+  if (reps < 1 || reps > 100000) return fail(DDI_EINVAL, "reps must lie in [1, 100000]");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  ddi::DevicePlan& P = plan->P;
+  hipEvent_t ev[ddi::kStages + 1];
+  for (int i = 0; i <= ddi::kStages; ++i) {
+    hipError_t e = hipEventCreate(&ev[i]);
+    if (e != hipSuccess) {
+      for (int j = 0; j < i; ++j) (void)hipEventDestroy(ev[j]);
+      return hip_fail(e, "hipEventCreate");
+    }
+  }
+  for (int i = 0; i < ddi::kStages; ++i) stage_ms[i] = 0.0;
+  ddi_status result = DDI_OK;
+  for (int r = 0; r < reps && result == DDI_OK; ++r) {
+    hipError_t e = P.mixed ? ddi::run_apply<float>(P, static_cast<const float*>(in_dev), static_cast<float*>(out_dev), sign, s, ev)
+                           : ddi::run_apply<double>(P, static_cast<const double*>(in_dev), static_cast<double*>(out_dev), sign, s, ev);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[ddi::kStages]);
+    if (e != hipSuccess) { result = hip_fail(e, "ddi_profile_apply"); break; }
+    for (int i = 0; i < ddi::kStages; ++i) {
+      float ms = 0.0f;
+      e = hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+      if (e != hipSuccess) { result = hip_fail(e, "hipEventElapsedTime"); break; }
+      stage_ms[i] += ms;
+    }
+  }
+  for (int i = 0; i <= ddi::kStages; ++i) (void)hipEventDestroy(ev[i]);
+  if (result == DDI_OK)
+    for (int i = 0; i < ddi::kStages; ++i) stage_ms[i] /= reps;
+  return result;
+}
+
+ddi_status ddi_type2(ddi_plan_t plan, const void* rho_dev, void* rhohat_dev, void* stream) {
+  ddi_status st = check_plan(plan);
+  if (st != DDI_OK) return st;
+  if (!rho_dev || !rhohat_dev) return fail(DDI_EINVAL, "NULL buffer");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  ddi::DevicePlan& P = plan->P;
+  hipError_t e;
+  if (P.mixed)
+    e = ddi::run_type2<float>(P, static_cast<const float*>(rho_dev), static_cast<ddi::Complex<float>*>(rhohat_dev),
+                              nullptr, P.H.cell, -1, s, nullptr);
+  else
+    e = ddi::run_type2<double>(P, static_cast<const double*>(rho_dev), static_cast<ddi::Complex<double>*>(rhohat_dev),
+                               nullptr, P.H.cell, -1, s, nullptr);
+  if (e != hipSuccess) return hip_fail(e, "ddi_type2 launch");
+  return DDI_OK;
+}
+
+ddi_status ddi_type1(ddi_plan_t plan, const void* g_dev, void* phi_dev, void* stream) {
+  ddi_status st = check_plan(plan);
+  if (st != DDI_OK) return st;
+  if (!g_dev || !phi_dev) return fail(DDI_EINVAL, "NULL buffer");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  ddi::DevicePlan& P = plan->P;
+  hipError_t e = P.mixed ? ddi::run_type1<float>(P, static_cast<const ddi::Complex<float>*>(g_dev), static_cast<float*>(phi_dev), +1, s, nullptr)
+                         : ddi::run_type1<double>(P, static_cast<const ddi::Complex<double>*>(g_dev), static_cast<double*>(phi_dev), +1, s, nullptr);
+  if (e != hipSuccess) return hip_fail(e, "ddi_type1 launch");
+  return DDI_OK;
+}
+
+ddi_status gpe_energy_grad(ddi_plan_t plan, const gpe_params* gp, const void* psi_dev, double E_out[5],
+                           void* grad_dev, void* stream) {
+  ddi_status st = check_plan(plan);
+  if (st != DDI_OK) return st;
+  if (!gp || !psi_dev || !E_out) return fail(DDI_EINVAL, "NULL argument");
+  if (!std::isfinite(gp->beta) || !std::isfinite(gp->lambda)) return fail(DDI_EINVAL, "beta and lambda must be finite");
+  ddi::DevicePlan& P = plan->P;
+  st = P.mixed ? ensure_gpe<float>(P) : ensure_gpe<double>(P);
+  if (st != DDI_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  double* E_dev = P.gpe_red + 8 * P.gpe_red_blocks + 8;
+  hipError_t e = P.mixed ? ddi::run_gpe_energy_grad<float>(P, *gp, static_cast<const ddi::Complex<float>*>(psi_dev), E_dev,
+                                                           static_cast<ddi::Complex<float>*>(grad_dev), s)
+                         : ddi::run_gpe_energy_grad<double>(P, *gp, static_cast<const ddi::Complex<double>*>(psi_dev), E_dev,
+                                                            static_cast<ddi::Complex<double>*>(grad_dev), s);
+  if (e != hipSuccess) return hip_fail(e, "gpe_energy_grad launch");
+  HIP_TRY(hipMemcpyAsync(E_out, E_dev, 5 * sizeof(double), hipMemcpyDeviceToHost, s), "copy energies");
+  HIP_TRY(hipStreamSynchronize(s), "gpe_energy_grad");
+  return DDI_OK;
+}
+
+ddi_status gpe_gf_step(ddi_plan_t plan, const gpe_params* gp, double dt, int32_t n_inner, const void* psi_in_dev,
+                       void* psi_out_dev, void* stream) {
+  ddi_status st = check_plan(plan);
+  if (st != DDI_OK) return st;
+  if (!gp || !psi_in_dev || !psi_out_dev) return fail(DDI_EINVAL, "NULL argument");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DDI_EINVAL, "dt must be positive");
+  if (n_inner < 0 || n_inner > 10000) return fail(DDI_EINVAL, "n_inner must lie in [0, 10000]");
+  ddi::DevicePlan& P = plan->P;
+  st = P.mixed ? ensure_gpe<float>(P) : ensure_gpe<double>(P);
+  if (st != DDI_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = P.mixed ? ddi::run_gf_step<float>(P, *gp, dt, n_inner, static_cast<const ddi::Complex<float>*>(psi_in_dev),
+                                                   static_cast<ddi::Complex<float>*>(psi_out_dev), s)
+                         : ddi::run_gf_step<double>(P, *gp, dt, n_inner, static_cast<const ddi::Complex<double>*>(psi_in_dev),
+                                                    static_cast<ddi::Complex<double>*>(psi_out_dev), s);
+  if (e != hipSuccess) return hip_fail(e, "gpe_gf_step launch");
+  return DDI_OK;
+}
+
+}  // extern "C"

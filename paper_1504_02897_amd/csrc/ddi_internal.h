@@ -1,0 +1,132 @@
+// Internal declarations shared by the plan builder, the kernels and the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ddi.h"
+
+namespace ddi {
+
+constexpr int kWMax = 16;          // largest kernel width
+constexpr int kTileZ = 8;          // spread tile extent along the last axis (registers per lane)
+
+// One quadrature node as seen by the spread / interpolation kernels: the first
+// fine-grid index of its support on each axis (already reduced mod n_fine) and
+// the separable kernel weights psi(l0 + i - tau) for i < w on each axis.
+template <typename T>
+struct alignas(16) NodeRec {
+  int32_t l0[3];
+  int32_t pad;
+  T w[3][kWMax];
+};
+
+// A unit of spread work: the nodes list[start, start+count) are summed into
+// the tile `tile`; slot < 0 writes the tile directly, otherwise a partial
+// tile is written to partial slot `slot` and summed by a reduce item.
+struct SpreadItem {
+  int32_t tile;
+  int32_t start;
+  int32_t count;
+  int32_t slot;
+};
+
+struct ReduceItem {
+  int32_t tile;
+  int32_t first_slot;
+  int32_t nslots;
+  int32_t pad;
+};
+
+// Host-side tables built by build_tables() (all FP64).
+struct HostTables {
+  int dim = 3;
+  int N[3] = {1, 1, 1};        // grid sizes on the internal 3-axis layout (N[0] = 1 in 2D)
+  int nf[3] = {1, 1, 1};       // oversampled FFT sizes
+  int W[3] = {1, 1, 1};        // kernel width per axis (1 on the unused 2D axis)
+  int tile[3] = {1, 1, 1};     // spread tile extents
+  int ntiles[3] = {1, 1, 1};
+  double h[3] = {1, 1, 1};
+  double L[3] = {0, 0, 0};
+  double cell = 1.0;           // prod(h)
+  int w = 0;
+  double es_beta = 0.0;
+  double kmax = 0.0;
+  int64_t m_nominal = 0;
+  int64_t M = 0;               // nodes kept
+  // per node, plan (sorted) order
+  std::vector<int32_t> index;  // [M][3]
+  std::vector<double> k;       // [M][3]
+  std::vector<double> c;       // [M]  W Uhat / (2 pi)^d
+  std::vector<int32_t> l0;     // [M][3]
+  std::vector<double> wts;     // [M][3][kWMax]
+  std::vector<double> deconv[3];   // 1/phihat per compact index, length N[a]
+  // spread schedule
+  std::vector<int32_t> list;       // node indices per tile, concatenated
+  std::vector<SpreadItem> items;
+  std::vector<ReduceItem> reduces;
+  int32_t nslots = 0;
+};
+
+// Builds every host table of a plan.  Returns an empty string on success or an error message.
+std::string build_tables(const ddi_params& p, HostTables& t, int* status);
+
+// Accurate e^{-2 pi i k / n}, k in [0, n), interleaved (re, im).
+std::vector<double> twiddle_table(int n);
+
+// ---------------------------------------------------------------- device side
+template <typename T>
+struct Complex {
+  T re, im;
+};
+
+// Device-resident plan state.
+struct DevicePlan {
+  HostTables H;
+  bool mixed = false;
+  int device = 0;
+  // tables
+  void* nodes = nullptr;         // NodeRec<T>[M]
+  double* c_scaled = nullptr;    // c_q * prod(h) [M]
+  double* deconv[3] = {nullptr, nullptr, nullptr};
+  int32_t* list = nullptr;
+  SpreadItem* items = nullptr;
+  ReduceItem* reduces = nullptr;
+  void* twiddles[11] = {};       // per log2(n): Complex<T>[n]
+  // workspace
+  void* fine = nullptr;          // Complex<T>[nf0*nf1*nf2]
+  void* gnodes = nullptr;        // Complex<T>[M]
+  void* partial = nullptr;       // Complex<T>[nslots][tile volume]
+  int64_t workspace_bytes = 0;
+  // GPE workspace (allocated on first use)
+  void* gpe_rho = nullptr;       // T[N]
+  void* gpe_phi = nullptr;       // T[N]
+  void* gpe_phit = nullptr;      // T[N]
+  void* gpe_c1 = nullptr;        // Complex<T>[N]
+  void* gpe_c2 = nullptr;        // Complex<T>[N]
+  double* gpe_red = nullptr;     // reduction scratch
+  int gpe_red_blocks = 0;
+};
+
+// Kernel launchers (kernels.hip), templated on the real type.
+template <typename T>
+hipError_t run_type2(DevicePlan& P, const T* rho, Complex<T>* out, const double* scale, double cscalar,
+                     int sign, hipStream_t s, hipEvent_t* ev);
+template <typename T>
+hipError_t run_type1(DevicePlan& P, const Complex<T>* g, T* phi, int sign, hipStream_t s, hipEvent_t* ev);
+template <typename T>
+hipError_t run_apply(DevicePlan& P, const T* rho, T* phi, int sign, hipStream_t s, hipEvent_t* ev);
+constexpr int kStages = 9;
+template <typename T>
+hipError_t run_gpe_energy_grad(DevicePlan& P, const gpe_params& gp, const Complex<T>* psi, double* E_dev,
+                               Complex<T>* grad, hipStream_t s);
+template <typename T>
+hipError_t run_gf_step(DevicePlan& P, const gpe_params& gp, double dt, int n_inner, const Complex<T>* psi_in,
+                       Complex<T>* psi_out, hipStream_t s);
+template <typename T>
+int gpe_reduction_blocks(const DevicePlan& P);
+
+}  // namespace ddi

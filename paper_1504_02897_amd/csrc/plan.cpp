@@ -1,0 +1,337 @@
+// Plan-time tables (host, FP64): quadrature of Eq. DDI-Trun1, Nyquist mask,
+// dipolar symbol (Eqs. DipKer, dipmn), exponential-of-semicircle kernel and
+// its Fourier transform, node binning and the tiled spread schedule.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "ddi_internal.h"
+
+namespace ddi {
+
+namespace {
+
+constexpr long double kPiL = 3.141592653589793238462643383279502884L;
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// n-point Gauss-Legendre rule on [-1, 1]: Newton's method on P_n evaluated by
+// the three-term recurrence, carried in long double.
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    long double z = cosl(kPiL * (i + 0.75L) / (n + 0.5L));
+    long double dp = 1.0L;
+    for (int it = 0; it < 100; ++it) {
+      long double p0 = 1.0L, p1 = z;
+      for (int j = 1; j < n; ++j) {
+        long double p2 = ((2 * j + 1) * z * p1 - j * p0) / (j + 1);
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) { p0 = 1.0L; p1 = z; }
+      dp = n * (z * p1 - p0) / (z * z - 1.0L);
+      long double dz = p1 / dp;
+      z -= dz;
+      if (fabsl(dz) < 1e-19L) break;
+    }
+    long double p0 = 1.0L, p1 = z;
+    for (int j = 1; j < n; ++j) {
+      long double p2 = ((2 * j + 1) * z * p1 - j * p0) / (j + 1);
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = n * (z * p1 - p0) / (z * z - 1.0L);
+    // nodes in increasing order
+    x[n - 1 - i] = static_cast<double>(z);
+    w[n - 1 - i] = static_cast<double>(2.0L / ((1.0L - z * z) * dp * dp));
+  }
+}
+
+// Exponential-of-semicircle kernel psi(z) = exp(beta (sqrt(1 - (2z/w)^2) - 1)), |z| < w/2.
+double es_kernel(double z, int w, double beta) {
+  double a = 2.0 * z / w;
+  double s = 1.0 - a * a;
+  if (s <= 0.0) return 0.0;
+  return std::exp(beta * (std::sqrt(s) - 1.0));
+}
+
+// phihat(m) = int psi(z) cos(2 pi m z / nf) dz over [-w/2, w/2], by a 128-point
+// Gauss-Legendre rule on each half (the integrand is even).
+double es_fourier(double m, int nf, int w, double beta, const std::vector<double>& gx,
+                  const std::vector<double>& gw) {
+  double half = 0.5 * w;
+  long double acc = 0.0L;
+  for (size_t i = 0; i < gx.size(); ++i) {
+    double z = 0.5 * half * (gx[i] + 1.0);
+    acc += (long double)gw[i] * es_kernel(z, w, beta) * std::cos(2.0 * M_PI * m * z / nf);
+  }
+  return static_cast<double>(2.0L * 0.5L * half * acc);
+}
+
+}  // namespace
+
+std::vector<double> twiddle_table(int n) {
+  std::vector<double> t(2 * n);
+  for (int k = 0; k < n; ++k) {
+    long double a = 2.0L * kPiL * k / n;
+    t[2 * k] = static_cast<double>(cosl(a));
+    t[2 * k + 1] = static_cast<double>(-sinl(a));
+  }
+  return t;
+}
+
+std::string build_tables(const ddi_params& p, HostTables& t, int* status) {
+  *status = DDI_EINVAL;
+  if (p.dim != 2 && p.dim != 3) return "dim must be 2 or 3";
+  const int d = p.dim;
+  for (int a = 0; a < d; ++a) {
+    if (!is_pow2(p.n[a])) return "grid sizes must be powers of two";
+    if (!(p.L[a] > 0.0) || !std::isfinite(p.L[a])) return "L must be positive and finite";
+  }
+  double nn = std::sqrt(p.dip_n[0] * p.dip_n[0] + p.dip_n[1] * p.dip_n[1] + p.dip_n[2] * p.dip_n[2]);
+  double nm = std::sqrt(p.dip_m[0] * p.dip_m[0] + p.dip_m[1] * p.dip_m[1] + p.dip_m[2] * p.dip_m[2]);
+  if (!(nn > 0.0) || !std::isfinite(nn)) return "dipole axis n must be a non-zero finite vector";
+  if (!std::isfinite(nm)) return "dipole axis m must be finite";
+  if (p.n_rad < 1 || p.n_azi < 1 || (d == 3 && p.n_pol < 1)) return "quadrature sizes must be positive";
+  if (p.n_rad > 65536 || p.n_azi > 65536 || (d == 3 && p.n_pol > 65536)) return "quadrature sizes too large";
+  if (p.prec != DDI_FP64 && p.prec != DDI_MIXED) return "prec must be DDI_FP64 or DDI_MIXED";
+  int w = p.kernel_width;
+  if (w == 0) {
+    if (!(p.tol > 0.0) || !(p.tol < 1.0)) return "tol must lie in (0, 1) when kernel_width is 0";
+    w = static_cast<int>(std::ceil(-std::log10(p.tol))) + 1;
+    w = std::min(kWMax, std::max(4, w));
+  }
+  if (w < 2 || w > kWMax) return "kernel_width must lie in [2, 16]";
+
+  *status = DDI_ENOTSUP;
+  // internal 3-axis layout: 2D grids live on axes 1 and 2
+  const int off = 3 - d;
+  for (int a = 0; a < 3; ++a) { t.N[a] = 1; t.nf[a] = 1; t.W[a] = 1; t.h[a] = 1.0; t.L[a] = 0.5; }
+  for (int a = 0; a < d; ++a) {
+    int64_t n = p.n[a];
+    if (n < (d == 3 ? 8 : 32) || n > 512) return "grid size per axis must lie in [8, 512] (3D) or [32, 512] (2D)";
+    t.N[off + a] = static_cast<int>(n);
+    t.nf[off + a] = static_cast<int>(2 * n);
+    t.W[off + a] = w;
+    t.L[off + a] = p.L[a];
+    t.h[off + a] = 2.0 * p.L[a] / n;
+    if (t.nf[off + a] < 2 * w) return "grid too small for the kernel width";
+  }
+  t.dim = d;
+  t.w = w;
+  t.es_beta = 2.30 * w;
+  t.cell = 1.0;
+  for (int a = 0; a < 3; ++a) t.cell *= (a >= off ? t.h[a] : 1.0);
+  if (d == 3) { t.tile[0] = 8; t.tile[1] = 8; t.tile[2] = kTileZ; }
+  else { t.tile[0] = 1; t.tile[1] = 64; t.tile[2] = kTileZ; }
+  for (int a = 0; a < 3; ++a) t.ntiles[a] = t.nf[a] / t.tile[a];
+
+  // ---------------------------------------------------------------- quadrature
+  double hp[3] = {0, 0, 0};      // h in paper axes
+  for (int a = 0; a < d; ++a) hp[a] = 2.0 * p.L[a] / p.n[a];
+  double kmax = p.kmax;
+  if (!(kmax > 0.0)) {
+    double s = 0.0;
+    for (int a = 0; a < d; ++a) s += 1.0 / (hp[a] * hp[a]);
+    kmax = M_PI * std::sqrt(s);
+  }
+  t.kmax = kmax;
+  double nv[3], mv[3];
+  // the axes are used as given: the paper prints its unit vectors to five digits
+  for (int i = 0; i < 3; ++i) nv[i] = p.dip_n[i];
+  if (nm > 0.0) for (int i = 0; i < 3; ++i) mv[i] = p.dip_m[i];
+  else for (int i = 0; i < 3; ++i) mv[i] = nv[i];
+
+  std::vector<double> tr, wr, tu, wu;
+  gauss_legendre(static_cast<int>(p.n_rad), tr, wr);
+  const int npol = d == 3 ? static_cast<int>(p.n_pol) : 1;
+  if (d == 3) gauss_legendre(npol, tu, wu);
+  const int nazi = static_cast<int>(p.n_azi);
+  std::vector<double> cphi(nazi), sphi(nazi);
+  for (int c = 0; c < nazi; ++c) {
+    double ph = 2.0 * M_PI * c / nazi;
+    cphi[c] = std::cos(ph);
+    sphi[c] = std::sin(ph);
+  }
+  const double wphi = 2.0 * M_PI / nazi;
+  const double inv2pid = 1.0 / std::pow(2.0 * M_PI, d);
+  t.m_nominal = static_cast<int64_t>(p.n_rad) * npol * nazi;
+
+  std::vector<int32_t> idx_nat;
+  std::vector<double> k_nat, c_nat;
+  for (int ia = 0; ia < p.n_rad; ++ia) {
+    double r = 0.5 * kmax * (1.0 + tr[ia]);
+    double wrad = 0.5 * kmax * wr[ia];
+    for (int ib = 0; ib < npol; ++ib) {
+      double u = d == 3 ? tu[ib] : 0.0;
+      double su = d == 3 ? std::sqrt(1.0 - u * u) : 1.0;
+      for (int ic = 0; ic < nazi; ++ic) {
+        double k[3];
+        double W;
+        if (d == 3) {
+          k[0] = r * su * cphi[ic];
+          k[1] = r * su * sphi[ic];
+          k[2] = r * u;
+          W = wrad * r * r * wu[ib] * wphi;
+        } else {
+          k[0] = r * cphi[ic];
+          k[1] = r * sphi[ic];
+          k[2] = 0.0;
+          W = wrad * r * wphi;
+        }
+        if (p.nyquist_mask) {
+          bool inside = true;
+          for (int a = 0; a < d; ++a) inside = inside && (std::fabs(k[a]) <= M_PI / hp[a]);
+          if (!inside) continue;
+        }
+        double U;
+        double kk = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+        if (d == 3) {
+          double kn = k[0] * nv[0] + k[1] * nv[1] + k[2] * nv[2];
+          double km = k[0] * mv[0] + k[1] * mv[1] + k[2] * mv[2];
+          U = 3.0 * kn * km / kk - (nv[0] * mv[0] + nv[1] * mv[1] + nv[2] * mv[2]);
+        } else {
+          double kn = k[0] * nv[0] + k[1] * nv[1];
+          double km = k[0] * mv[0] + k[1] * mv[1];
+          U = 3.0 * (kn * km - nv[2] * mv[2] * kk) / (2.0 * std::sqrt(kk));
+        }
+        idx_nat.push_back(ia);
+        idx_nat.push_back(d == 3 ? ib : 0);
+        idx_nat.push_back(ic);
+        k_nat.push_back(k[0]);
+        k_nat.push_back(k[1]);
+        k_nat.push_back(k[2]);
+        c_nat.push_back(W * U * inv2pid);
+      }
+    }
+  }
+  const int64_t M = static_cast<int64_t>(c_nat.size());
+  if (M == 0) { *status = DDI_EINVAL; return "no quadrature node lies inside the Nyquist box"; }
+  if (M > (int64_t(1) << 30)) return "too many quadrature nodes";
+  t.M = M;
+
+  // ---------------------------------------------------------------- kernel geometry per node
+  std::vector<int32_t> l0_nat(3 * M);
+  std::vector<double> w_nat(static_cast<size_t>(3 * kWMax) * M, 0.0);
+  std::vector<int64_t> home(M);
+  for (int64_t q = 0; q < M; ++q) {
+    int64_t tile_id = 0;
+    for (int a = 0; a < 3; ++a) {
+      int l0 = 0;
+      double* wq = &w_nat[(q * 3 + a) * kWMax];
+      if (t.N[a] == 1) {
+        wq[0] = 1.0;
+      } else {
+        int pa = a - off;                       // paper axis
+        double tq = k_nat[3 * q + pa] * t.h[a]; // in [-pi, pi] when masked
+        double tau = tq * t.nf[a] / (2.0 * M_PI);
+        l0 = static_cast<int>(std::ceil(tau - 0.5 * w));
+        for (int i = 0; i < w; ++i) wq[i] = es_kernel(l0 + i - tau, w, t.es_beta);
+        l0 %= t.nf[a];
+        if (l0 < 0) l0 += t.nf[a];
+      }
+      l0_nat[3 * q + a] = l0;
+      tile_id = tile_id * t.ntiles[a] + l0 / t.tile[a];
+    }
+    home[q] = tile_id;
+  }
+  // sort nodes by the tile that holds the start of their support (stable)
+  std::vector<int64_t> perm(M);
+  std::iota(perm.begin(), perm.end(), 0);
+  std::stable_sort(perm.begin(), perm.end(), [&](int64_t x, int64_t y) { return home[x] < home[y]; });
+  t.index.resize(3 * M);
+  t.k.resize(3 * M);
+  t.c.resize(M);
+  t.l0.resize(3 * M);
+  t.wts.resize(static_cast<size_t>(3 * kWMax) * M);
+  for (int64_t s = 0; s < M; ++s) {
+    int64_t q = perm[s];
+    for (int a = 0; a < 3; ++a) {
+      t.index[3 * s + a] = idx_nat[3 * q + a];
+      t.k[3 * s + a] = k_nat[3 * q + a];
+      t.l0[3 * s + a] = l0_nat[3 * q + a];
+    }
+    t.c[s] = c_nat[q];
+    std::memcpy(&t.wts[static_cast<size_t>(s) * 3 * kWMax], &w_nat[static_cast<size_t>(q) * 3 * kWMax],
+                sizeof(double) * 3 * kWMax);
+  }
+
+  // ---------------------------------------------------------------- deconvolution 1/phihat
+  {
+    std::vector<double> gx, gw;
+    gauss_legendre(128, gx, gw);
+    for (int a = 0; a < 3; ++a) {
+      t.deconv[a].assign(t.N[a], 1.0);
+      if (t.N[a] == 1) continue;
+      for (int c = 0; c < t.N[a]; ++c) {
+        double m = c - t.N[a] / 2;
+        t.deconv[a][c] = 1.0 / es_fourier(m, t.nf[a], w, t.es_beta, gx, gw);
+      }
+    }
+  }
+
+  // ---------------------------------------------------------------- spread schedule
+  const int64_t ntile_total = static_cast<int64_t>(t.ntiles[0]) * t.ntiles[1] * t.ntiles[2];
+  if (ntile_total > (int64_t(1) << 30)) return "fine grid too large";
+  auto touched = [&](int64_t s, int a, int* out) {
+    int cnt = 0;
+    for (int i = 0; i < t.W[a]; ++i) {
+      int pos = (t.l0[3 * s + a] + i) % t.nf[a];
+      int tl = pos / t.tile[a];
+      bool seen = false;
+      for (int j = 0; j < cnt; ++j) seen = seen || out[j] == tl;
+      if (!seen) out[cnt++] = tl;
+    }
+    return cnt;
+  };
+  std::vector<int64_t> count(ntile_total + 1, 0);
+  int tx[kWMax], ty[kWMax], tz[kWMax];
+  for (int pass = 0; pass < 2; ++pass) {
+    if (pass == 1) {
+      for (int64_t i = 0, run = 0; i <= ntile_total; ++i) { int64_t c = count[i]; count[i] = run; run += c; }
+      if (count[ntile_total] > (int64_t(1) << 31) - 1) return "spread schedule too large";
+      t.list.assign(count[ntile_total], 0);
+    }
+    std::vector<int64_t> fill;
+    if (pass == 1) fill.assign(count.begin(), count.end());
+    for (int64_t s = 0; s < M; ++s) {
+      int nx = touched(s, 0, tx), ny = touched(s, 1, ty), nz = touched(s, 2, tz);
+      for (int i = 0; i < nx; ++i)
+        for (int j = 0; j < ny; ++j)
+          for (int k = 0; k < nz; ++k) {
+            int64_t tid = (static_cast<int64_t>(tx[i]) * t.ntiles[1] + ty[j]) * t.ntiles[2] + tz[k];
+            if (pass == 0) count[tid]++;
+            else t.list[fill[tid]++] = static_cast<int32_t>(s);
+          }
+    }
+  }
+  const int chunk = 256;
+  t.items.clear();
+  t.reduces.clear();
+  int32_t slot = 0;
+  for (int64_t tid = 0; tid < ntile_total; ++tid) {
+    int64_t beg = count[tid], n = count[tid + 1] - count[tid];
+    if (n <= chunk) {
+      t.items.push_back({static_cast<int32_t>(tid), static_cast<int32_t>(beg), static_cast<int32_t>(n), -1});
+    } else {
+      int nch = static_cast<int>((n + chunk - 1) / chunk);
+      t.reduces.push_back({static_cast<int32_t>(tid), slot, nch, 0});
+      for (int c = 0; c < nch; ++c) {
+        int64_t b = beg + static_cast<int64_t>(c) * chunk;
+        int64_t e = std::min(beg + n, b + chunk);
+        t.items.push_back({static_cast<int32_t>(tid), static_cast<int32_t>(b), static_cast<int32_t>(e - b), slot++});
+      }
+    }
+  }
+  // heaviest items first so that the long ones start early
+  std::stable_sort(t.items.begin(), t.items.end(),
+                   [](const SpreadItem& x, const SpreadItem& y) { return x.count > y.count; });
+  t.nslots = slot;
+  *status = DDI_OK;
+  return "";
+}
+
+}  // namespace ddi
