@@ -19,7 +19,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libddi.so")
-SOURCES = ["plan.cpp", "kernels.hip", "capi.cpp"]
+SOURCES = ["plan.cpp", "fft.hip", "nufft.hip", "gpe.hip", "capi.cpp"]
 
 
 def hipcc():

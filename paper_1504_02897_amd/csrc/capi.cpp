@@ -44,6 +44,7 @@ hipError_t upload(X** dst, const X* src, size_t count, hipStream_t s, int64_t& b
 
 void free_plan(ddi::DevicePlan& P) {
   void* ptrs[] = {P.nodes, P.c_scaled, P.deconv[0], P.deconv[1], P.deconv[2], P.list, P.items, P.reduces,
+                  P.interp_items, P.interp_direct,
                   P.fine, P.gnodes, P.partial, P.gpe_rho, P.gpe_phi, P.gpe_phit, P.gpe_c1, P.gpe_c2, P.gpe_red};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -76,6 +77,8 @@ ddi_status build_device(ddi::DevicePlan& P, hipStream_t s, std::vector<ddi::Node
   HIP_TRY(upload(&P.list, H.list.data(), H.list.size(), s, bytes), "upload spread lists");
   HIP_TRY(upload(&P.items, H.items.data(), H.items.size(), s, bytes), "upload spread items");
   HIP_TRY(upload(&P.reduces, H.reduces.data(), H.reduces.size(), s, bytes), "upload spread reduces");
+  HIP_TRY(upload(&P.interp_items, H.interp_items.data(), H.interp_items.size(), s, bytes), "upload interp groups");
+  HIP_TRY(upload(&P.interp_direct, H.interp_direct.data(), H.interp_direct.size(), s, bytes), "upload interp list");
   // twiddles for every FFT length used: fine grid sizes and the unpadded sizes
   tws.assign(11, {});
   for (int a = 0; a < 3; ++a) {
@@ -164,6 +167,18 @@ ddi_status ddi_plan(const ddi_params* params, void* stream, ddi_plan_t* out) {
     return fail(DDI_EDEVICE, "no HIP device");
   }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  {
+    // grouped interpolation stages its region in LDS; without room for it, every node goes direct
+    int max_lds = 0;
+    if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, P.device) != hipSuccess) max_lds = 0;
+    const size_t elem = P.mixed ? 2 * sizeof(float) : 2 * sizeof(double);
+    const size_t need = static_cast<size_t>(P.H.ireg[0]) * P.H.ireg[1] * P.H.ireg[2] * elem;
+    if (need > static_cast<size_t>(max_lds)) {
+      for (const ddi::InterpItem& it : P.H.interp_items)
+        for (int32_t c = 0; c < it.count; ++c) P.H.interp_direct.push_back(it.start + c);
+      P.H.interp_items.clear();
+    }
+  }
   ddi_status ds;
   std::vector<ddi::NodeRec<double>> rd;
   std::vector<ddi::NodeRec<float>> rf;

@@ -34,6 +34,15 @@ struct SpreadItem {
   int32_t slot;
 };
 
+// A group of nodes (plan-order range) whose supports start in one block of ib^3
+// cells; their supports lie in the region org + [0, ireg) (mod n_fine), staged in LDS.
+struct InterpItem {
+  int32_t start;
+  int32_t count;
+  int32_t org[3];
+  int32_t pad[3];
+};
+
 struct ReduceItem {
   int32_t tile;
   int32_t first_slot;
@@ -49,6 +58,8 @@ struct HostTables {
   int W[3] = {1, 1, 1};        // kernel width per axis (1 on the unused 2D axis)
   int tile[3] = {1, 1, 1};     // spread tile extents
   int ntiles[3] = {1, 1, 1};
+  int ib[3] = {1, 1, 1};       // interpolation group block extents
+  int ireg[3] = {1, 1, 1};     // region extents ib + W - 1
   double h[3] = {1, 1, 1};
   double L[3] = {0, 0, 0};
   double cell = 1.0;           // prod(h)
@@ -69,6 +80,9 @@ struct HostTables {
   std::vector<SpreadItem> items;
   std::vector<ReduceItem> reduces;
   int32_t nslots = 0;
+  // interpolation schedule
+  std::vector<InterpItem> interp_items;   // grouped nodes (LDS-staged region)
+  std::vector<int32_t> interp_direct;     // nodes interpolated straight from the grid
 };
 
 // Builds every host table of a plan.  Returns an empty string on success or an error message.
@@ -83,6 +97,21 @@ struct Complex {
   T re, im;
 };
 
+// Remap a block index so that consecutive logical blocks run on the same XCD:
+// blocks are dispatched round-robin over the 8 XCDs, each with its own L2.
+__device__ inline int xcd_remap(int b, int nb) {
+  constexpr int X = 8;
+  const int x = b % X, local = b / X;
+  const int base = nb / X, rem = nb % X;
+  return x * base + (x < rem ? x : rem) + local;
+}
+
+#define DDI_CHECK(x)                 \
+  do {                               \
+    hipError_t e_ = (x);             \
+    if (e_ != hipSuccess) return e_; \
+  } while (0)
+
 // Device-resident plan state.
 struct DevicePlan {
   HostTables H;
@@ -95,6 +124,9 @@ struct DevicePlan {
   int32_t* list = nullptr;
   SpreadItem* items = nullptr;
   ReduceItem* reduces = nullptr;
+  InterpItem* interp_items = nullptr;
+  int32_t* interp_direct = nullptr;
+  bool interp_lds_ready = false;
   void* twiddles[11] = {};       // per log2(n): Complex<T>[n]
   // workspace
   void* fine = nullptr;          // Complex<T>[nf0*nf1*nf2]

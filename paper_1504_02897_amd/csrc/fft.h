@@ -1,0 +1,36 @@
+// Batched FFT passes used by the NUFFT (fine grid) and by the GPE kernels (unpadded grid).
+#pragma once
+
+#include "ddi_internal.h"
+
+namespace ddi {
+
+// Last-axis pass modes: R2C_PAD reads a real compact grid times the deconvolution
+// factors into the active half of each oversampled line; C2C is a plain complex
+// transform; C2R_TRUNC keeps the active modes, applies the deconvolution factors
+// and writes the real part to a compact grid.
+enum ContigMode { R2C_PAD = 0, C2C = 1, C2R_TRUNC = 2 };
+
+// In-place transforms of length n along axis 0 or 1 of a [d0][d1][d2] complex
+// array.  The other non-last axis runs over n_o lines (the compact modes of an
+// oversampled axis when o_compact); in_c / out_c: only the nc active positions
+// of each line are read / written (exp(SIGN 2 pi i jk/n)).
+template <typename T, int SIGN>
+hipError_t launch_strided(int n, Complex<T>* F, int axis, int d0, int d1, int d2, int n_o, int o_compact, int nc,
+                          int in_c, int out_c, const Complex<T>* tw, hipStream_t s);
+
+// Transforms of length n along the last axis; lines run over the n0 x n1 compact
+// grid (R2C_PAD, C2R_TRUNC: mapped into a [d0][d1][n] oversampled array) or over
+// d0 x d1 = n0 x n1 directly (C2C).
+template <typename T, int SIGN, int MODE>
+hipError_t launch_contig(int n, const void* in, void* out, int n0, int n1, int d0, int d1, int nc2,
+                         const double* D0, const double* D1, const double* D2, const Complex<T>* tw,
+                         hipStream_t s);
+
+inline int ilog2(int n) {
+  int l = 0;
+  while ((1 << l) < n) ++l;
+  return l;
+}
+
+}  // namespace ddi

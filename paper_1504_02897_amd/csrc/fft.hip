@@ -1,0 +1,371 @@
+// Batched 1D FFT passes on gfx950 (wave64): Stockham radix-4/8/16 with the
+// butterflies in registers and one LDS exchange per pass.  Lines along the
+// last (contiguous) axis fuse the NUFFT prologue (deconvolution, zero padding)
+// or epilogue (truncation, deconvolution, real part); lines along the strided
+// axes are processed in bundles of consecutive last-axis indices so that every
+// global access is coalesced, and skip the zero (input) or unused (output)
+// half of the oversampled line.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fft.h"
+
+namespace ddi {
+
+template <typename T>
+using C = Complex<T>;
+
+template <typename T>
+__device__ __forceinline__ C<T> cmul(C<T> a, C<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ C<T> cadd(C<T> a, C<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ C<T> csub(C<T> a, C<T> b) { return {a.re - b.re, a.im - b.im}; }
+
+// cos(2 pi j / 16) from the first-quadrant values
+__host__ __device__ constexpr double cos_16(int j) {
+  j &= 15;
+  const double q[5] = {1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173, 0.0};
+  return j <= 4 ? q[j] : (j <= 8 ? -q[8 - j] : (j <= 12 ? -q[j - 8] : q[16 - j]));
+}
+
+// ------------------------------------------------------------------ in-register DFT of size R <= 16
+// out[k] = sum_r v[r] exp(SIGN 2 pi i r k / R), iterative radix-2 decimation in time.
+template <int R>
+__device__ __forceinline__ constexpr int bitrev(int i) {
+  int r = 0;
+  for (int b = 1; b < R; b <<= 1) { r = (r << 1) | (i & 1); i >>= 1; }
+  return r;
+}
+
+template <typename T, int R, int SIGN>
+__device__ __forceinline__ void dft_regs(C<T>* v) {
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int j = bitrev<R>(i);
+    if (j > i) { C<T> t = v[i]; v[i] = v[j]; v[j] = t; }
+  }
+#pragma unroll
+  for (int m = 2; m <= R; m <<= 1) {
+#pragma unroll
+    for (int k = 0; k < R; k += m) {
+#pragma unroll
+      for (int j = 0; j < m / 2; ++j) {
+        const int idx = j * (16 / m);      // angle index in units of 2 pi / 16, in [0, 8)
+        C<T> b = v[k + j + m / 2];
+        C<T> t;
+        if (idx == 0) {
+          t = b;
+        } else if (idx == 4) {             // exp(SIGN i pi/2) = SIGN i
+          t = SIGN > 0 ? C<T>{-b.im, b.re} : C<T>{b.im, -b.re};
+        } else {
+          const T c = static_cast<T>(cos_16(idx));
+          const T s = static_cast<T>(SIGN * cos_16(idx - 4));
+          t = {b.re * c - b.im * s, b.re * s + b.im * c};
+        }
+        C<T> a = v[k + j];
+        v[k + j] = cadd(a, t);
+        v[k + j + m / 2] = csub(a, t);
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ radix plans
+template <int N> struct RadixPlan;
+template <> struct RadixPlan<8> { static constexpr int R1 = 8, R2 = 1, R3 = 1; };
+template <> struct RadixPlan<16> { static constexpr int R1 = 4, R2 = 4, R3 = 1; };
+template <> struct RadixPlan<32> { static constexpr int R1 = 8, R2 = 4, R3 = 1; };
+template <> struct RadixPlan<64> { static constexpr int R1 = 8, R2 = 8, R3 = 1; };
+template <> struct RadixPlan<128> { static constexpr int R1 = 16, R2 = 8, R3 = 1; };
+template <> struct RadixPlan<256> { static constexpr int R1 = 16, R2 = 16, R3 = 1; };
+template <> struct RadixPlan<512> { static constexpr int R1 = 8, R2 = 8, R3 = 8; };
+template <> struct RadixPlan<1024> { static constexpr int R1 = 16, R2 = 16, R3 = 4; };
+
+// One Stockham pass (radix R, Ns = product of earlier radices) over LDS, for the
+// butterflies j = j0 + TL*b owned by this thread.  The thread's registers hold
+// R1 values (R1/R butterflies of R values).
+template <typename T, int N, int R1, int R, int SIGN, typename Addr>
+__device__ __forceinline__ void stockham_load(C<T>* lds, Addr addr, int j0, int Ns, const C<T>* __restrict__ tw,
+                                              C<T>* v) {
+  constexpr int TL = N / R1;
+  constexpr int NB = R1 / R;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int j = j0 + TL * b;
+    const int jm = j % Ns;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      C<T> x = lds[addr(j + r * (N / R))];
+      if (r > 0) {
+        C<T> w = tw[(r * jm * (N / (Ns * R))) & (N - 1)];
+        if (SIGN > 0) w.im = -w.im;
+        x = cmul(x, w);
+      }
+      v[b * R + r] = x;
+    }
+    dft_regs<T, R, SIGN>(v + b * R);
+  }
+}
+
+template <typename T, int N, int R1, int R, typename Addr>
+__device__ __forceinline__ void stockham_store(C<T>* lds, Addr addr, int j0, int Ns, const C<T>* v) {
+  constexpr int TL = N / R1;
+  constexpr int NB = R1 / R;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int j = j0 + TL * b;
+    const int idxD = (j / Ns) * Ns * R + (j % Ns);
+#pragma unroll
+    for (int r = 0; r < R; ++r) lds[addr(idxD + r * Ns)] = v[b * R + r];
+  }
+}
+
+// Full line FFT.  On entry v[r] = x[j0 + r*TL] (r < R1).  On exit the thread
+// holds the outputs k = j + r*(N/Rlast), j = j0 + TL*b, in v[b*Rlast + r].
+template <typename T, int N, int SIGN, typename Addr>
+__device__ __forceinline__ void line_fft(C<T>* lds, Addr addr, int j0, const C<T>* __restrict__ tw, C<T>* v) {
+  using P = RadixPlan<N>;
+  dft_regs<T, P::R1, SIGN>(v);
+  if constexpr (P::R2 > 1) {
+    stockham_store<T, N, P::R1, P::R1>(lds, addr, j0, 1, v);
+    __syncthreads();
+    stockham_load<T, N, P::R1, P::R2, SIGN>(lds, addr, j0, P::R1, tw, v);
+    if constexpr (P::R3 > 1) {
+      __syncthreads();
+      stockham_store<T, N, P::R1, P::R2>(lds, addr, j0, P::R1, v);
+      __syncthreads();
+      stockham_load<T, N, P::R1, P::R3, SIGN>(lds, addr, j0, P::R1 * P::R2, tw, v);
+    }
+  }
+}
+
+template <int N>
+struct LineOut {
+  using P = RadixPlan<N>;
+  static constexpr int RL = P::R3 > 1 ? P::R3 : (P::R2 > 1 ? P::R2 : P::R1);
+  static constexpr int TL = N / P::R1;
+  // output index held in v[i] by thread j0
+  __device__ static __forceinline__ int k(int j0, int i) {
+    const int b = i / RL, r = i % RL;
+    return j0 + TL * b + r * (N / RL);
+  }
+};
+
+// Modes m = c - nc/2, c in [0, nc), sit at fine index m mod n: the active set is
+// [0, nc - nc/2) and [n - nc/2, n).
+__device__ __forceinline__ bool active(int k, int n, int nc) { return k < nc - nc / 2 || k >= n - nc / 2; }
+// compact index c in [0, nc) -> fine index of mode c - nc/2
+__device__ __forceinline__ int fmap(int c, int n, int nc) { return c < nc / 2 ? n - nc / 2 + c : c - nc / 2; }
+// fine index -> compact index (only for active k)
+__device__ __forceinline__ int cmap(int k, int n, int nc) { return k < nc - nc / 2 ? k + nc / 2 : k - (n - nc / 2); }
+
+
+// ------------------------------------------------------------------ strided-axis FFT pass
+// Lines along axis `axis` (0 or 1) of a [d0][d1][d2] complex array, B consecutive
+// z per workgroup.  The other non-z axis runs over n_o lines (compact when
+// o_compact: index o -> fine index fmap(o, d_o, n_o)).  in_compact / out_compact:
+// only the N_c active positions of the line are read (rest zero) / written.
+template <typename T, int N, int SIGN>
+__global__ void __launch_bounds__(256) k_fft_strided(C<T>* __restrict__ F, int axis, int d0, int d1, int d2,
+                                                     int n_o, int o_compact, int nc_axis, int in_compact,
+                                                     int out_compact, const C<T>* __restrict__ tw, int B) {
+  extern __shared__ unsigned char smem_raw[];
+  C<T>* lds = reinterpret_cast<C<T>*>(smem_raw);
+  using P = RadixPlan<N>;
+  constexpr int TL = N / P::R1;
+  const int b = threadIdx.x % B;
+  const int j0 = threadIdx.x / B;
+  const int zblocks = d2 / B;
+  const int blk = blockIdx.x;
+  const int o = blk / zblocks;
+  const int z = (blk % zblocks) * B + b;
+  const int d_o = axis == 0 ? d1 : d0;
+  const int of = o_compact ? fmap(o, d_o, n_o) : o;
+  int64_t base, stride;
+  if (axis == 0) { base = static_cast<int64_t>(of) * d2 + z; stride = static_cast<int64_t>(d1) * d2; }
+  else { base = static_cast<int64_t>(of) * d1 * d2 + z; stride = d2; }
+  auto addr = [B, b](int k) { return k * B + b; };
+  C<T> v[P::R1];
+#pragma unroll
+  for (int r = 0; r < P::R1; ++r) {
+    const int k = j0 + r * TL;
+    if (in_compact && !active(k, N, nc_axis)) v[r] = C<T>{0, 0};
+    else v[r] = F[base + k * stride];
+  }
+  line_fft<T, N, SIGN>(lds, addr, j0, tw, v);
+#pragma unroll
+  for (int i = 0; i < P::R1; ++i) {
+    const int k = LineOut<N>::k(j0, i);
+    if (!out_compact || active(k, N, nc_axis)) F[base + k * stride] = v[i];
+  }
+}
+
+// ------------------------------------------------------------------ last-axis (contiguous) FFT pass
+
+
+// Lines along axis 2.  Line l -> (o0, o1); in R2C_PAD / C2R_TRUNC modes (o0, o1)
+// run over the compact N0 x N1 grid and map to fine indices; in C2C they run
+// over d0 x d1 directly.  R2C_PAD: input real rho[N0][N1][N2] times the
+// deconvolution factors, placed at the active positions of a length-N line,
+// output complex line.  C2R_TRUNC: input complex line, output
+// Re(line[fmap(c2)]) times the deconvolution factors into phi[N0][N1][N2].
+template <typename T, int N, int SIGN, int MODE>
+__global__ void __launch_bounds__(256) k_fft_contig(const void* in, void* out,
+                                                    int n0, int n1, int d0, int d1, int nc2,
+                                                    const double* __restrict__ D0, const double* __restrict__ D1,
+                                                    const double* __restrict__ D2,
+                                                    const C<T>* __restrict__ tw, int B, int nlines) {
+  extern __shared__ unsigned char smem_raw[];
+  C<T>* lds = reinterpret_cast<C<T>*>(smem_raw);
+  using P = RadixPlan<N>;
+  constexpr int TL = N / P::R1;
+  constexpr int LS = N + N / P::R1;      // padded line stride in LDS
+  const int j0 = threadIdx.x % TL;
+  const int lb = threadIdx.x / TL;
+  const int line = blockIdx.x * B + lb;
+  const bool valid = line < nlines;
+  const int o0 = valid ? line / n1 : 0;
+  const int o1 = valid ? line % n1 : 0;
+  C<T>* my = lds + lb * LS;
+  auto addr = [](int k) { return k + k / RadixPlan<N>::R1; };
+  C<T> v[P::R1];
+  if (MODE == R2C_PAD) {
+    const T* rho = reinterpret_cast<const T*>(in);
+    const double s01 = D0[o0] * D1[o1];
+    const int64_t rb = (static_cast<int64_t>(o0) * n1 + o1) * nc2;
+#pragma unroll
+    for (int r = 0; r < P::R1; ++r) {
+      const int k = j0 + r * TL;
+      if (valid && active(k, N, nc2)) {
+        const int c2 = cmap(k, N, nc2);
+        v[r] = C<T>{static_cast<T>(static_cast<double>(rho[rb + c2]) * s01 * D2[c2]), T(0)};
+      } else {
+        v[r] = C<T>{0, 0};
+      }
+    }
+  } else {
+    const C<T>* F = reinterpret_cast<const C<T>*>(in);
+    int64_t lbase;
+    if (MODE == C2C) lbase = static_cast<int64_t>(line) * N;
+    else lbase = (static_cast<int64_t>(fmap(o0, d0, n0)) * d1 + fmap(o1, d1, n1)) * N;
+#pragma unroll
+    for (int r = 0; r < P::R1; ++r) {
+      const int k = j0 + r * TL;
+      v[r] = valid ? F[lbase + k] : C<T>{0, 0};
+    }
+  }
+  line_fft<T, N, SIGN>(my, addr, j0, tw, v);
+  if (!valid) return;
+  if (MODE == C2R_TRUNC) {
+    T* phi = reinterpret_cast<T*>(out);
+    const double s01 = D0[o0] * D1[o1];
+    const int64_t rb = (static_cast<int64_t>(o0) * n1 + o1) * nc2;
+#pragma unroll
+    for (int i = 0; i < P::R1; ++i) {
+      const int k = LineOut<N>::k(j0, i);
+      if (active(k, N, nc2)) {
+        const int c2 = cmap(k, N, nc2);
+        phi[rb + c2] = static_cast<T>(static_cast<double>(v[i].re) * s01 * D2[c2]);
+      }
+    }
+  } else {
+    C<T>* F = reinterpret_cast<C<T>*>(out);
+    int64_t lbase;
+    if (MODE == C2C) lbase = static_cast<int64_t>(line) * N;
+    else lbase = (static_cast<int64_t>(fmap(o0, d0, n0)) * d1 + fmap(o1, d1, n1)) * N;
+#pragma unroll
+    for (int i = 0; i < P::R1; ++i) F[lbase + LineOut<N>::k(j0, i)] = v[i];
+  }
+}
+
+// ------------------------------------------------------------------ dispatch
+template <typename T, int N, int SIGN>
+static hipError_t launch_strided_n(C<T>* F, int axis, int d0, int d1, int d2, int n_o, int o_compact, int nc,
+                                   int in_c, int out_c, const C<T>* tw, hipStream_t s) {
+  constexpr int TL = N / RadixPlan<N>::R1;
+  int B = 256 / TL;
+  while (B > d2) B >>= 1;
+  const size_t shm = static_cast<size_t>(B) * N * sizeof(C<T>);
+  const int blocks = n_o * (d2 / B);
+  hipLaunchKernelGGL((k_fft_strided<T, N, SIGN>), dim3(blocks), dim3(B * TL), shm, s, F, axis, d0, d1, d2, n_o,
+                     o_compact, nc, in_c, out_c, tw, B);
+  return hipGetLastError();
+}
+
+template <typename T, int SIGN>
+hipError_t launch_strided(int n, C<T>* F, int axis, int d0, int d1, int d2, int n_o, int o_compact, int nc,
+                                 int in_c, int out_c, const C<T>* tw, hipStream_t s) {
+  switch (n) {
+    case 8: return launch_strided_n<T, 8, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, tw, s);
+    case 16: return launch_strided_n<T, 16, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, tw, s);
+    case 32: return launch_strided_n<T, 32, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, tw, s);
+    case 64: return launch_strided_n<T, 64, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, tw, s);
+    case 128: return launch_strided_n<T, 128, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, tw, s);
+    case 256: return launch_strided_n<T, 256, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, tw, s);
+    case 512: return launch_strided_n<T, 512, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, tw, s);
+    case 1024: return launch_strided_n<T, 1024, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, tw, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T, int N, int SIGN, int MODE>
+static hipError_t launch_contig_n(const void* in, void* out, int n0, int n1, int d0, int d1, int nc2,
+                                  const double* D0, const double* D1, const double* D2, const C<T>* tw,
+                                  hipStream_t s) {
+  constexpr int TL = N / RadixPlan<N>::R1;
+  constexpr int LS = N + N / RadixPlan<N>::R1;
+  int B = 256 / TL;
+  while (B > 1 && static_cast<size_t>(B) * LS * sizeof(C<T>) > 65536) B >>= 1;
+  const int nlines = n0 * n1;
+  const size_t shm = static_cast<size_t>(B) * LS * sizeof(C<T>);
+  const int blocks = (nlines + B - 1) / B;
+  hipLaunchKernelGGL((k_fft_contig<T, N, SIGN, MODE>), dim3(blocks), dim3(B * TL), shm, s, in, out, n0, n1, d0, d1,
+                     nc2, D0, D1, D2, tw, B, nlines);
+  return hipGetLastError();
+}
+
+template <typename T, int SIGN, int MODE>
+hipError_t launch_contig(int n, const void* in, void* out, int n0, int n1, int d0, int d1, int nc2,
+                                const double* D0, const double* D1, const double* D2, const C<T>* tw,
+                                hipStream_t s) {
+  switch (n) {
+    case 8: return launch_contig_n<T, 8, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, D0, D1, D2, tw, s);
+    case 16: return launch_contig_n<T, 16, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, D0, D1, D2, tw, s);
+    case 32: return launch_contig_n<T, 32, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, D0, D1, D2, tw, s);
+    case 64: return launch_contig_n<T, 64, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, D0, D1, D2, tw, s);
+    case 128: return launch_contig_n<T, 128, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, D0, D1, D2, tw, s);
+    case 256: return launch_contig_n<T, 256, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, D0, D1, D2, tw, s);
+    case 512: return launch_contig_n<T, 512, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, D0, D1, D2, tw, s);
+    case 1024: return launch_contig_n<T, 1024, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, D0, D1, D2, tw, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+#define DDI_INST_STRIDED(T, S)                                                                                  \
+  template hipError_t launch_strided<T, S>(int, C<T>*, int, int, int, int, int, int, int, int, int, const C<T>*, \
+                                           hipStream_t);
+#define DDI_INST_CONTIG(T, S, M)                                                                                \
+  template hipError_t launch_contig<T, S, M>(int, const void*, void*, int, int, int, int, int, const double*,   \
+                                             const double*, const double*, const C<T>*, hipStream_t);
+DDI_INST_STRIDED(double, 1)
+DDI_INST_STRIDED(double, -1)
+DDI_INST_STRIDED(float, 1)
+DDI_INST_STRIDED(float, -1)
+DDI_INST_CONTIG(double, 1, R2C_PAD)
+DDI_INST_CONTIG(double, -1, R2C_PAD)
+DDI_INST_CONTIG(float, 1, R2C_PAD)
+DDI_INST_CONTIG(float, -1, R2C_PAD)
+DDI_INST_CONTIG(double, 1, C2C)
+DDI_INST_CONTIG(double, -1, C2C)
+DDI_INST_CONTIG(float, 1, C2C)
+DDI_INST_CONTIG(float, -1, C2C)
+DDI_INST_CONTIG(double, 1, C2R_TRUNC)
+DDI_INST_CONTIG(double, -1, C2R_TRUNC)
+DDI_INST_CONTIG(float, 1, C2R_TRUNC)
+DDI_INST_CONTIG(float, -1, C2R_TRUNC)
+
+}  // namespace ddi

@@ -1,0 +1,400 @@
+// GPE kernels (Sec. 1, Eq. energy; Sec. 3.2 energy split; Sec. 3.1 gradient flow):
+// density, spectral kinetic energy and Laplacian through the batched FFT passes,
+// energy sums with FP64 block reductions (fixed order, deterministic), the
+// gradient dE/dconj(psi), and the stabilised backward-Euler Fourier step.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fft.h"
+
+namespace ddi {
+
+template <typename T>
+using C = Complex<T>;
+
+// ------------------------------------------------------------------ GPE kernels
+// Grid helpers on the unpadded N0 x N1 x N2 grid (N0 = 1 in 2D).
+struct GridGeo {
+  int N0, N1, N2;
+  double L0, L1, L2, h0, h1, h2;
+  double g0, g1, g2;          // trap frequencies per internal axis
+};
+
+__device__ __forceinline__ void grid_index(int64_t i, const GridGeo& G, int& a, int& b, int& c) {
+  c = static_cast<int>(i % G.N2);
+  b = static_cast<int>((i / G.N2) % G.N1);
+  a = static_cast<int>(i / (static_cast<int64_t>(G.N2) * G.N1));
+}
+
+template <typename T>
+__device__ __forceinline__ double trap_v(int64_t i, const GridGeo& G, const T* __restrict__ Vext) {
+  if (Vext) return static_cast<double>(Vext[i]);
+  int a, b, c;
+  grid_index(i, G, a, b, c);
+  const double x = -G.L0 + a * G.h0, y = -G.L1 + b * G.h1, z = -G.L2 + c * G.h2;
+  return 0.5 * (G.g0 * G.g0 * x * x + G.g1 * G.g1 * y * y + G.g2 * G.g2 * z * z);
+}
+
+__device__ __forceinline__ double mu2_of(int64_t i, const GridGeo& G) {
+  int a, b, c;
+  grid_index(i, G, a, b, c);
+  const double pa = a < G.N0 / 2 ? a : a - G.N0;
+  const double pb = b < G.N1 / 2 ? b : b - G.N1;
+  const double pc = c < G.N2 / 2 ? c : c - G.N2;
+  const double ma = M_PI * pa / G.L0, mb = M_PI * pb / G.L1, mc = M_PI * pc / G.L2;
+  return (G.N0 > 1 ? ma * ma : 0.0) + mb * mb + mc * mc;
+}
+
+constexpr int kRedThreads = 256;
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_density(const C<T>* __restrict__ psi, T* __restrict__ rho, int64_t n) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const C<T> p = psi[i];
+    rho[i] = static_cast<T>(static_cast<double>(p.re) * p.re + static_cast<double>(p.im) * p.im);
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_copy(const C<T>* __restrict__ a, C<T>* __restrict__ b, int64_t n) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    b[i] = a[i];
+}
+
+// Block-level FP64 sum of up to 4 values; partial sums to red[block*4 + j].
+__device__ __forceinline__ void block_sum4(double v[4], double* __restrict__ red) {
+  __shared__ double sh[4][kRedThreads / 64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[j] += __shfl_xor(v[j], off, 64);
+    if (lane == 0) sh[j][wv] = v[j];
+  }
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    double s = 0.0;
+    for (int w = 0; w < kRedThreads / 64; ++w) s += sh[threadIdx.x][w];
+    red[blockIdx.x * 4 + threadIdx.x] = s;
+  }
+}
+
+// sums of mu^2 |psihat|^2 (slot 0); also writes lap = 1/2 mu^2 psihat / prod(N) in place
+template <typename T>
+__global__ void __launch_bounds__(kRedThreads) k_kinetic(C<T>* __restrict__ ph, int64_t n, GridGeo G,
+                                                          double inv_ntot, double* __restrict__ red) {
+  double v[4] = {0, 0, 0, 0};
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const double m2 = mu2_of(i, G);
+    const C<T> p = ph[i];
+    v[0] += m2 * (static_cast<double>(p.re) * p.re + static_cast<double>(p.im) * p.im);
+    const double f = 0.5 * m2 * inv_ntot;
+    ph[i] = C<T>{static_cast<T>(f * p.re), static_cast<T>(f * p.im)};
+  }
+  block_sum4(v, red);
+}
+
+// sums of V rho (1), rho^2 (2), Phi rho (3)
+template <typename T>
+__global__ void __launch_bounds__(kRedThreads) k_energy_terms(const T* __restrict__ rho, const T* __restrict__ phi,
+                                                               const T* __restrict__ Vext, int64_t n, GridGeo G,
+                                                               double* __restrict__ red) {
+  double v[4] = {0, 0, 0, 0};
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const double r = rho[i];
+    v[1] += trap_v(i, G, Vext) * r;
+    v[2] += r * r;
+    v[3] += static_cast<double>(phi[i]) * r;
+  }
+  block_sum4(v, red);
+}
+
+// E_out[0..4] from the block partials (fixed order -> deterministic)
+__global__ void k_energy_final(const double* __restrict__ red_kin, const double* __restrict__ red_terms, int nblocks,
+                               double cell, double inv_ntot, double beta, double lam, double* __restrict__ E) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s[4] = {0, 0, 0, 0};
+  for (int b = 0; b < nblocks; ++b) {
+    s[0] += red_kin[b * 4 + 0];
+    s[1] += red_terms[b * 4 + 1];
+    s[2] += red_terms[b * 4 + 2];
+    s[3] += red_terms[b * 4 + 3];
+  }
+  E[0] = 0.5 * cell * inv_ntot * s[0];
+  E[1] = cell * s[1];
+  E[2] = 0.5 * beta * cell * s[2];
+  E[3] = 0.5 * lam * cell * s[3];
+  E[4] = E[0] + E[1] + E[2] + E[3];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_grad(const C<T>* __restrict__ psi, const C<T>* __restrict__ lap,
+                                              const T* __restrict__ rho, const T* __restrict__ phi,
+                                              const T* __restrict__ phit, const T* __restrict__ Vext, int64_t n,
+                                              GridGeo G, double cell, double beta, double lam,
+                                              C<T>* __restrict__ grad) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const double pot = trap_v(i, G, Vext) + beta * static_cast<double>(rho[i]) +
+                       0.5 * lam * (static_cast<double>(phi[i]) + static_cast<double>(phit[i]));
+    const C<T> p = psi[i];
+    const C<T> l = lap[i];
+    grad[i] = C<T>{static_cast<T>(cell * (static_cast<double>(l.re) + pot * p.re)),
+                   static_cast<T>(cell * (static_cast<double>(l.im) + pot * p.im))};
+  }
+}
+
+// B = V + beta rho + lam Phi (into bout), block max/min partials to red[b*4+0/1]
+template <typename T>
+__global__ void __launch_bounds__(kRedThreads) k_gf_coeff(const T* __restrict__ rho, const T* __restrict__ phi,
+                                                           const T* __restrict__ Vext, int64_t n, GridGeo G,
+                                                           double beta, double lam, T* __restrict__ bout,
+                                                           double* __restrict__ red) {
+  double mx = -1e300, mn = 1e300;
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const double B = trap_v(i, G, Vext) + beta * static_cast<double>(rho[i]) + lam * static_cast<double>(phi[i]);
+    bout[i] = static_cast<T>(B);
+    mx = fmax(mx, B);
+    mn = fmin(mn, B);
+  }
+  __shared__ double sx[kRedThreads / 64], sn[kRedThreads / 64];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    mx = fmax(mx, __shfl_xor(mx, off, 64));
+    mn = fmin(mn, __shfl_xor(mn, off, 64));
+  }
+  if ((threadIdx.x & 63) == 0) { sx[threadIdx.x >> 6] = mx; sn[threadIdx.x >> 6] = mn; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kRedThreads / 64; ++w) { mx = fmax(mx, sx[w]); mn = fmin(mn, sn[w]); }
+    mx = fmax(mx, sx[0]);
+    mn = fmin(mn, sn[0]);
+    red[blockIdx.x * 4 + 0] = mx;
+    red[blockIdx.x * 4 + 1] = mn;
+  }
+}
+
+// scal[0] = alpha = (max + min)/2
+__global__ void k_gf_alpha(const double* __restrict__ red, int nblocks, double* __restrict__ scal) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double mx = -1e300, mn = 1e300;
+  for (int b = 0; b < nblocks; ++b) { mx = fmax(mx, red[b * 4]); mn = fmin(mn, red[b * 4 + 1]); }
+  scal[0] = 0.5 * (mx + mn);
+}
+
+// r = (alpha - B) phi
+template <typename T>
+__global__ void __launch_bounds__(256) k_gf_residual(const C<T>* __restrict__ phi, const T* __restrict__ B,
+                                                     const double* __restrict__ scal, int64_t n,
+                                                     C<T>* __restrict__ r) {
+  const double alpha = scal[0];
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const double f = alpha - static_cast<double>(B[i]);
+    const C<T> p = phi[i];
+    r[i] = C<T>{static_cast<T>(f * p.re), static_cast<T>(f * p.im)};
+  }
+}
+
+// rhat <- (rhs0 + rhat) / (1/dt + alpha + mu^2/2) / prod(N)   (the 1/prod(N) of the inverse FFT folded in)
+template <typename T>
+__global__ void __launch_bounds__(256) k_gf_solve(C<T>* __restrict__ rh, const C<T>* __restrict__ rhs0,
+                                                  const double* __restrict__ scal, int64_t n, GridGeo G, double dt,
+                                                  double inv_ntot) {
+  const double alpha = scal[0];
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const double den = (1.0 / dt + alpha + 0.5 * mu2_of(i, G)) / inv_ntot;
+    const C<T> a = rhs0[i], b = rh[i];
+    rh[i] = C<T>{static_cast<T>((static_cast<double>(a.re) + b.re) / den),
+                 static_cast<T>((static_cast<double>(a.im) + b.im) / den)};
+  }
+}
+
+// x <- x * f
+template <typename T>
+__global__ void __launch_bounds__(256) k_scale(C<T>* __restrict__ x, int64_t n, double f) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const C<T> p = x[i];
+    x[i] = C<T>{static_cast<T>(f * p.re), static_cast<T>(f * p.im)};
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kRedThreads) k_norm2(const C<T>* __restrict__ x, int64_t n,
+                                                       double* __restrict__ red) {
+  double v[4] = {0, 0, 0, 0};
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const C<T> p = x[i];
+    v[0] += static_cast<double>(p.re) * p.re + static_cast<double>(p.im) * p.im;
+  }
+  block_sum4(v, red);
+}
+
+// x <- x / sqrt(cell * sum)
+template <typename T>
+__global__ void __launch_bounds__(256) k_normalise(C<T>* __restrict__ x, int64_t n, const double* __restrict__ red,
+                                                   int nblocks, double cell) {
+  __shared__ double f;
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int b = 0; b < nblocks; ++b) s += red[b * 4];
+    f = 1.0 / sqrt(cell * s);
+  }
+  __syncthreads();
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const C<T> p = x[i];
+    x[i] = C<T>{static_cast<T>(f * p.re), static_cast<T>(f * p.im)};
+  }
+}
+
+static GridGeo geo_of(const HostTables& H, const gpe_params& gp) {
+  GridGeo G;
+  G.N0 = H.N[0]; G.N1 = H.N[1]; G.N2 = H.N[2];
+  G.L0 = H.L[0]; G.L1 = H.L[1]; G.L2 = H.L[2];
+  G.h0 = H.h[0]; G.h1 = H.h[1]; G.h2 = H.h[2];
+  if (H.dim == 3) { G.g0 = gp.gamma[0]; G.g1 = gp.gamma[1]; G.g2 = gp.gamma[2]; }
+  else { G.g0 = 0.0; G.g1 = gp.gamma[0]; G.g2 = gp.gamma[1]; }
+  return G;
+}
+
+template <typename T>
+int gpe_reduction_blocks(const DevicePlan& P) {
+  const int64_t n = static_cast<int64_t>(P.H.N[0]) * P.H.N[1] * P.H.N[2];
+  int64_t b = (n + kRedThreads * 8 - 1) / (kRedThreads * 8);
+  if (b > 2048) b = 2048;
+  if (b < 1) b = 1;
+  return static_cast<int>(b);
+}
+
+// In-place complex 3D FFT of an unpadded N0 x N1 x N2 grid.
+template <typename T, int SIGN>
+static hipError_t fft3_full(DevicePlan& P, C<T>* X, hipStream_t s) {
+  const HostTables& H = P.H;
+  const C<T>* tw2 = reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.N[2])]);
+  DDI_CHECK((launch_contig<T, SIGN, C2C>(H.N[2], X, X, H.N[0], H.N[1], H.N[0], H.N[1], H.N[2], nullptr, nullptr,
+                                         nullptr, tw2, s)));
+  DDI_CHECK((launch_strided<T, SIGN>(H.N[1], X, 1, H.N[0], H.N[1], H.N[2], H.N[0], 0, H.N[1], 0, 0,
+                                     reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.N[1])]), s)));
+  if (H.N[0] > 1) {
+    DDI_CHECK((launch_strided<T, SIGN>(H.N[0], X, 0, H.N[0], H.N[1], H.N[2], H.N[1], 0, H.N[0], 0, 0,
+                                       reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.N[0])]), s)));
+  }
+  return hipSuccess;
+}
+
+static int ew_blocks(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  return static_cast<int>(b > 16384 ? 16384 : b);
+}
+
+template <typename T>
+hipError_t run_gpe_energy_grad(DevicePlan& P, const gpe_params& gp, const Complex<T>* psi, double* E_dev,
+                               Complex<T>* grad, hipStream_t s) {
+  const HostTables& H = P.H;
+  const int64_t n = static_cast<int64_t>(H.N[0]) * H.N[1] * H.N[2];
+  const GridGeo G = geo_of(H, gp);
+  const double inv_ntot = 1.0 / static_cast<double>(n);
+  const int nb = P.gpe_red_blocks;
+  T* rho = reinterpret_cast<T*>(P.gpe_rho);
+  T* phi = reinterpret_cast<T*>(P.gpe_phi);
+  T* phit = reinterpret_cast<T*>(P.gpe_phit);
+  C<T>* c1 = reinterpret_cast<C<T>*>(P.gpe_c1);
+  const T* Vext = reinterpret_cast<const T*>(gp.V_dev);
+  double* red_kin = P.gpe_red;
+  double* red_terms = P.gpe_red + 4 * nb;
+  hipLaunchKernelGGL((k_density<T>), dim3(ew_blocks(n)), dim3(256), 0, s, psi, rho, n);
+  DDI_CHECK(hipGetLastError());
+  DDI_CHECK(run_apply<T>(P, rho, phi, +1, s, nullptr));
+  hipLaunchKernelGGL((k_copy<T>), dim3(ew_blocks(n)), dim3(256), 0, s, psi, c1, n);
+  DDI_CHECK(hipGetLastError());
+  DDI_CHECK((fft3_full<T, -1>(P, c1, s)));
+  hipLaunchKernelGGL((k_kinetic<T>), dim3(nb), dim3(kRedThreads), 0, s, c1, n, G, inv_ntot, red_kin);
+  DDI_CHECK(hipGetLastError());
+  hipLaunchKernelGGL((k_energy_terms<T>), dim3(nb), dim3(kRedThreads), 0, s, rho, phi, Vext, n, G, red_terms);
+  DDI_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(64), 0, s, red_kin, red_terms, nb, H.cell, inv_ntot, gp.beta,
+                     gp.lambda, E_dev);
+  DDI_CHECK(hipGetLastError());
+  if (grad) {
+    DDI_CHECK(run_apply<T>(P, rho, phit, -1, s, nullptr));
+    DDI_CHECK((fft3_full<T, +1>(P, c1, s)));     // c1 = -1/2 Lap psi
+    hipLaunchKernelGGL((k_grad<T>), dim3(ew_blocks(n)), dim3(256), 0, s, psi, c1, rho, phi, phit, Vext, n, G, H.cell,
+                       gp.beta, gp.lambda, grad);
+    DDI_CHECK(hipGetLastError());
+  }
+  return hipSuccess;
+}
+
+template <typename T>
+hipError_t run_gf_step(DevicePlan& P, const gpe_params& gp, double dt, int n_inner, const Complex<T>* psi_in,
+                       Complex<T>* psi_out, hipStream_t s) {
+  const HostTables& H = P.H;
+  const int64_t n = static_cast<int64_t>(H.N[0]) * H.N[1] * H.N[2];
+  const GridGeo G = geo_of(H, gp);
+  const double inv_ntot = 1.0 / static_cast<double>(n);
+  const int nb = P.gpe_red_blocks;
+  T* rho = reinterpret_cast<T*>(P.gpe_rho);
+  T* phi = reinterpret_cast<T*>(P.gpe_phi);
+  T* Bc = reinterpret_cast<T*>(P.gpe_phit);
+  C<T>* rhs0 = reinterpret_cast<C<T>*>(P.gpe_c1);
+  C<T>* r = reinterpret_cast<C<T>*>(P.gpe_c2);
+  const T* Vext = reinterpret_cast<const T*>(gp.V_dev);
+  double* red = P.gpe_red;
+  double* scal = P.gpe_red + 8 * nb;
+  hipLaunchKernelGGL((k_density<T>), dim3(ew_blocks(n)), dim3(256), 0, s, psi_in, rho, n);
+  DDI_CHECK(hipGetLastError());
+  DDI_CHECK(run_apply<T>(P, rho, phi, +1, s, nullptr));
+  hipLaunchKernelGGL((k_gf_coeff<T>), dim3(nb), dim3(kRedThreads), 0, s, rho, phi, Vext, n, G, gp.beta, gp.lambda,
+                     Bc, red);
+  DDI_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(k_gf_alpha, dim3(1), dim3(64), 0, s, red, nb, scal);
+  DDI_CHECK(hipGetLastError());
+  // rhs0 = FFT(psi_in) / dt
+  hipLaunchKernelGGL((k_copy<T>), dim3(ew_blocks(n)), dim3(256), 0, s, psi_in, rhs0, n);
+  DDI_CHECK(hipGetLastError());
+  DDI_CHECK((fft3_full<T, -1>(P, rhs0, s)));
+  hipLaunchKernelGGL((k_scale<T>), dim3(ew_blocks(n)), dim3(256), 0, s, rhs0, n, 1.0 / dt);
+  DDI_CHECK(hipGetLastError());
+  if (psi_out != psi_in) {
+    hipLaunchKernelGGL((k_copy<T>), dim3(ew_blocks(n)), dim3(256), 0, s, psi_in, psi_out, n);
+    DDI_CHECK(hipGetLastError());
+  }
+  for (int it = 0; it < n_inner; ++it) {
+    hipLaunchKernelGGL((k_gf_residual<T>), dim3(ew_blocks(n)), dim3(256), 0, s, psi_out, Bc, scal, n, r);
+    DDI_CHECK(hipGetLastError());
+    DDI_CHECK((fft3_full<T, -1>(P, r, s)));
+    hipLaunchKernelGGL((k_gf_solve<T>), dim3(ew_blocks(n)), dim3(256), 0, s, r, rhs0, scal, n, G, dt, inv_ntot);
+    DDI_CHECK(hipGetLastError());
+    DDI_CHECK((fft3_full<T, +1>(P, r, s)));
+    hipLaunchKernelGGL((k_copy<T>), dim3(ew_blocks(n)), dim3(256), 0, s, r, psi_out, n);
+    DDI_CHECK(hipGetLastError());
+  }
+  hipLaunchKernelGGL((k_norm2<T>), dim3(nb), dim3(kRedThreads), 0, s, psi_out, n, red);
+  DDI_CHECK(hipGetLastError());
+  hipLaunchKernelGGL((k_normalise<T>), dim3(ew_blocks(n)), dim3(256), 0, s, psi_out, n, red, nb, H.cell);
+  return hipGetLastError();
+}
+
+
+template hipError_t run_gpe_energy_grad<double>(DevicePlan&, const gpe_params&, const Complex<double>*, double*,
+                                                Complex<double>*, hipStream_t);
+template hipError_t run_gpe_energy_grad<float>(DevicePlan&, const gpe_params&, const Complex<float>*, double*,
+                                               Complex<float>*, hipStream_t);
+template hipError_t run_gf_step<double>(DevicePlan&, const gpe_params&, double, int, const Complex<double>*,
+                                        Complex<double>*, hipStream_t);
+template hipError_t run_gf_step<float>(DevicePlan&, const gpe_params&, double, int, const Complex<float>*,
+                                       Complex<float>*, hipStream_t);
+template int gpe_reduction_blocks<double>(const DevicePlan&);
+template int gpe_reduction_blocks<float>(const DevicePlan&);
+
+}  // namespace ddi

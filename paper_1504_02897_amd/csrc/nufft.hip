@@ -1,0 +1,493 @@
+// NUFFT halves of the DDI operator on gfx950 (Sec. 2.1, Eqs. DDI-Con, DDI-Trun1).
+//
+//   type-2 (grid -> nodes): deconvolve + zero-pad fused into the first FFT pass, pruned
+//     3-pass FFT on the oversampled grid, interpolation at the quadrature nodes (one wave per
+//     node, compile-time kernel width so that every load of a support row is in flight at
+//     once), weights g_q = c_q prod(h) rhohat_q fused into the epilogue.
+//   type-1 (nodes -> grid): tile-owned spread (a wave owns an 8 x 8 x 8 block of the fine grid
+//     in registers and sums the nodes whose support meets it, staged 64 at a time in LDS as
+//     tile-relative weight vectors; no atomics), hot tiles split into chunks whose partial tiles
+//     are summed in a fixed order by a reduce kernel; pruned 3-pass FFT with truncation,
+//     deconvolution and real part fused into the last pass.
+// Kernel weights are tabulated per node at plan time: nothing transcendental runs per apply.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fft.h"
+
+namespace ddi {
+
+template <typename T>
+using C = Complex<T>;
+
+// ------------------------------------------------------------------ interpolation
+// A wave interpolates NS = 64/SL nodes at once: SL sub-lanes per node, sub-lane u owning the
+// support row z = l0z + u, looping over the (x, y) support; the partial sums of a node are
+// then reduced over its SL sub-lanes (log2 SL shuffle steps shared by all NS nodes).
+template <int W>
+struct InterpShape {
+  static constexpr int SL = W <= 4 ? 4 : (W <= 8 ? 8 : 16);
+  static constexpr int NS = 64 / SL;
+};
+
+// Grouped nodes: the workgroup stages the support region of its group (IB + W - 1 cells
+// per axis; 1 on the unused axis of a 2D grid) in LDS once.  Region strides are
+// compile-time, so every LDS read uses an immediate offset from one base address.
+template <typename T, int W0, int W, int IB>
+__global__ void __launch_bounds__(256) k_interp_lds(const C<T>* __restrict__ F, const NodeRec<T>* __restrict__ nodes,
+                                                    const InterpItem* __restrict__ items, int nf0, int nf1, int nf2,
+                                                    const double* __restrict__ scale, double sscalar,
+                                                    C<T>* __restrict__ out) {
+  constexpr int SL = InterpShape<W>::SL, NS = InterpShape<W>::NS;
+  constexpr int R = IB + W - 1;
+  constexpr int R0 = W0 == 1 ? 1 : IB + W0 - 1;
+  extern __shared__ unsigned char smem_raw[];
+  C<T>* reg = reinterpret_cast<C<T>*>(smem_raw);
+  // items are pre-ordered so that round-robin dispatch gives each XCD one region of equal work
+  const InterpItem it = items[blockIdx.x];
+  if (it.count == 0) return;                 // padding item
+  for (int i = threadIdx.x; i < R0 * R * R; i += 256) {
+    const int rz = i % R;
+    const int t = i / R;
+    const int ry = t % R, rx = t / R;
+    int gx = it.org[0] + rx;
+    if (gx >= nf0) gx -= nf0;
+    int gy = it.org[1] + ry;
+    if (gy >= nf1) gy -= nf1;
+    int gz = it.org[2] + rz;
+    if (gz >= nf2) gz -= nf2;
+    reg[i] = F[(static_cast<uint32_t>(gx) * nf1 + gy) * nf2 + gz];
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int sl = lane / SL, u = lane % SL;
+  const bool zin = u < W;
+  for (int n0 = wv * NS; n0 < it.count; n0 += 4 * NS) {
+    const int n = n0 + sl;
+    const bool valid = n < it.count;
+    const int64_t q = static_cast<int64_t>(it.start) + (valid ? n : it.count - 1);
+    const NodeRec<T>* nd = nodes + q;
+    int lx = nd->l0[0] - it.org[0];
+    if (lx < 0) lx += nf0;
+    int ly = nd->l0[1] - it.org[1];
+    if (ly < 0) ly += nf1;
+    int lz = nd->l0[2] - it.org[2];
+    if (lz < 0) lz += nf2;
+    double wx[W0], wy[W];
+#pragma unroll
+    for (int i = 0; i < W0; ++i) wx[i] = static_cast<double>(nd->w[0][i]);
+#pragma unroll
+    for (int i = 0; i < W; ++i) wy[i] = static_cast<double>(nd->w[1][i]);
+    const double wz = zin ? static_cast<double>(nd->w[2][u]) : 0.0;
+    const C<T>* p = reg + (lx * R + ly) * R + lz + (zin ? u : 0);
+    double are = 0.0, aim = 0.0;
+#pragma unroll
+    for (int iy = 0; iy < W; ++iy) {
+      double sre = 0.0, sim = 0.0;
+#pragma unroll
+      for (int ix = 0; ix < W0; ++ix) {
+        const C<T> f = p[ix * R * R + iy * R];
+        sre += wx[ix] * static_cast<double>(f.re);
+        sim += wx[ix] * static_cast<double>(f.im);
+      }
+      are += wy[iy] * sre;
+      aim += wy[iy] * sim;
+    }
+    are *= wz;
+    aim *= wz;
+#pragma unroll
+    for (int off = SL / 2; off > 0; off >>= 1) {
+      are += __shfl_xor(are, off, 64);
+      aim += __shfl_xor(aim, off, 64);
+    }
+    if (u == 0 && valid) {
+      const double s = scale ? scale[q] * sscalar : sscalar;
+      out[q] = C<T>{static_cast<T>(s * are), static_cast<T>(s * aim)};
+    }
+  }
+}
+
+// Nodes without enough neighbours in their group block: the same lane layout, reading the
+// oversampled grid directly (x-plane and y-row offsets precomputed with the periodic wrap).
+template <typename T, int W0, int W>
+__global__ void __launch_bounds__(256) k_interp(const C<T>* __restrict__ F, const NodeRec<T>* __restrict__ nodes,
+                                                const int32_t* __restrict__ list, int64_t nlist, int nf0, int nf1,
+                                                int nf2, const double* __restrict__ scale, double sscalar,
+                                                C<T>* __restrict__ out) {
+  constexpr int SL = InterpShape<W>::SL, NS = InterpShape<W>::NS;
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int sl = lane / SL, u = lane % SL;
+  const bool zin = u < W;
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t li = (static_cast<int64_t>(blk) * 4 + wv) * NS + sl;
+  const bool valid = li < nlist;
+  const int64_t q = list[valid ? li : nlist - 1];
+  const NodeRec<T>* nd = nodes + q;
+  const int lx = nd->l0[0], ly = nd->l0[1], lz = nd->l0[2];
+  double wx[W0], wy[W];
+  uint32_t xo[W0];
+#pragma unroll
+  for (int i = 0; i < W0; ++i) {
+    wx[i] = static_cast<double>(nd->w[0][i]);
+    int gx = lx + i;
+    if (gx >= nf0) gx -= nf0;
+    xo[i] = static_cast<uint32_t>(gx) * nf1 * nf2;
+  }
+#pragma unroll
+  for (int i = 0; i < W; ++i) wy[i] = static_cast<double>(nd->w[1][i]);
+  const double wz = zin ? static_cast<double>(nd->w[2][u]) : 0.0;
+  int gz = lz + (zin ? u : 0);
+  if (gz >= nf2) gz -= nf2;
+  double are = 0.0, aim = 0.0;
+#pragma unroll
+  for (int iy = 0; iy < W; ++iy) {
+    int gy = ly + iy;
+    if (gy >= nf1) gy -= nf1;
+    const C<T>* row = F + (static_cast<uint32_t>(gy) * nf2 + gz);
+    double sre = 0.0, sim = 0.0;
+#pragma unroll
+    for (int ix = 0; ix < W0; ++ix) {
+      const C<T> f = row[xo[ix]];
+      sre += wx[ix] * static_cast<double>(f.re);
+      sim += wx[ix] * static_cast<double>(f.im);
+    }
+    are += wy[iy] * sre;
+    aim += wy[iy] * sim;
+  }
+  are *= wz;
+  aim *= wz;
+#pragma unroll
+  for (int off = SL / 2; off > 0; off >>= 1) {
+    are += __shfl_xor(are, off, 64);
+    aim += __shfl_xor(aim, off, 64);
+  }
+  if (u == 0 && valid) {
+    const double s = scale ? scale[q] * sscalar : sscalar;
+    out[q] = C<T>{static_cast<T>(s * are), static_cast<T>(s * aim)};
+  }
+}
+
+// ------------------------------------------------------------------ spread
+// One wave per work item; tile TX x TY x kTileZ with TX*TY = 64 lanes, each lane owning
+// kTileZ points along the last axis in registers.
+template <typename T, bool KAHAN, int TX, int TY>
+__global__ void __launch_bounds__(64) k_spread(C<T>* __restrict__ F, C<T>* __restrict__ partial,
+                                               const NodeRec<T>* __restrict__ nodes, const C<T>* __restrict__ g,
+                                               const int32_t* __restrict__ list,
+                                               const SpreadItem* __restrict__ items, int nf0, int nf1, int nf2,
+                                               int nt1, int nt2, int w0, int w1, int w2) {
+  static_assert(TX * TY == 64, "one wave per tile");
+  constexpr int TZ = kTileZ;
+  __shared__ T sx[64][TX];
+  __shared__ T sy[64][TY];
+  __shared__ T sz[64][TZ];
+  __shared__ C<T> sg[64];
+  const int lane = threadIdx.x;
+  const SpreadItem it = items[blockIdx.x];
+  if (it.tile < 0) return;                   // padding item
+  const int tz = it.tile % nt2;
+  const int ty = (it.tile / nt2) % nt1;
+  const int tx = it.tile / (nt2 * nt1);
+  const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
+  const int lxo = lane / TY, lyo = lane % TY;
+  C<T> acc[TZ];
+  C<T> cmp[TZ];
+#pragma unroll
+  for (int i = 0; i < TZ; ++i) {
+    acc[i] = C<T>{0, 0};
+    cmp[i] = C<T>{0, 0};
+  }
+  for (int base = 0; base < it.count; base += 64) {
+    const int n = it.count - base < 64 ? it.count - base : 64;
+    // stage the weights of up to 64 nodes restricted to this tile (one node per lane);
+    // loads are unconditional (index clamped into the record) so that all are in flight
+    if (lane < n) {
+      const int q = list[it.start + base + lane];
+      const NodeRec<T>* nd = nodes + q;
+      const int l0x = nd->l0[0], l0y = nd->l0[1], l0z = nd->l0[2];
+      const C<T> gq = g[q];
+      int dx = x0 - l0x;
+      if (dx < 0) dx += nf0;
+      int dy = y0 - l0y;
+      if (dy < 0) dy += nf1;
+      int dz = z0 - l0z;
+      if (dz < 0) dz += nf2;
+      T vx[TX], vy[TY], vz[TZ];
+#pragma unroll
+      for (int i = 0; i < TX; ++i) {
+        int d = dx + i;
+        if (d >= nf0) d -= nf0;
+        vx[i] = nd->w[0][d < kWMax ? d : kWMax - 1];
+        vx[i] = d < w0 ? vx[i] : T(0);
+      }
+#pragma unroll
+      for (int i = 0; i < TY; ++i) {
+        int d = dy + i;
+        if (d >= nf1) d -= nf1;
+        vy[i] = nd->w[1][d < kWMax ? d : kWMax - 1];
+        vy[i] = d < w1 ? vy[i] : T(0);
+      }
+#pragma unroll
+      for (int i = 0; i < TZ; ++i) {
+        int d = dz + i;
+        if (d >= nf2) d -= nf2;
+        vz[i] = nd->w[2][d < kWMax ? d : kWMax - 1];
+        vz[i] = d < w2 ? vz[i] : T(0);
+      }
+#pragma unroll
+      for (int i = 0; i < TX; ++i) sx[lane][i] = vx[i];
+#pragma unroll
+      for (int i = 0; i < TY; ++i) sy[lane][i] = vy[i];
+#pragma unroll
+      for (int i = 0; i < TZ; ++i) sz[lane][i] = vz[i];
+      sg[lane] = gq;
+    }
+    __syncthreads();
+    for (int e = 0; e < n; ++e) {
+      const C<T> gq = sg[e];
+      T wz[TZ];
+#pragma unroll
+      for (int i = 0; i < TZ; ++i) wz[i] = sz[e][i];
+      const T wxy = sx[e][lxo] * sy[e][lyo];
+      const C<T> p = {gq.re * wxy, gq.im * wxy};
+#pragma unroll
+      for (int i = 0; i < TZ; ++i) {
+        if (KAHAN) {
+          T yr = p.re * wz[i] - cmp[i].re;
+          T tr = acc[i].re + yr;
+          cmp[i].re = (tr - acc[i].re) - yr;
+          acc[i].re = tr;
+          T yi = p.im * wz[i] - cmp[i].im;
+          T ti = acc[i].im + yi;
+          cmp[i].im = (ti - acc[i].im) - yi;
+          acc[i].im = ti;
+        } else {
+          acc[i].re += p.re * wz[i];
+          acc[i].im += p.im * wz[i];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  const int x = x0 + lxo, y = y0 + lyo;
+  if (it.slot < 0) {
+    C<T>* row = F + (static_cast<int64_t>(x) * nf1 + y) * nf2 + z0;
+#pragma unroll
+    for (int i = 0; i < TZ; ++i) row[i] = acc[i];
+  } else {
+    C<T>* pt = partial + static_cast<int64_t>(it.slot) * 64 * TZ;
+#pragma unroll
+    for (int i = 0; i < TZ; ++i) pt[i * 64 + lane] = acc[i];
+  }
+}
+
+// Sum the partial tiles of each split tile in slot order (deterministic); one thread per point.
+template <typename T, int TX, int TY>
+__global__ void __launch_bounds__(64 * kTileZ) k_spread_reduce(C<T>* __restrict__ F,
+                                                               const C<T>* __restrict__ partial,
+                                                               const ReduceItem* __restrict__ red, int nf1, int nf2,
+                                                               int nt1, int nt2) {
+  const int lane = threadIdx.x & 63;
+  const int i = threadIdx.x >> 6;
+  const ReduceItem r = red[blockIdx.x];
+  const int tz = r.tile % nt2;
+  const int ty = (r.tile / nt2) % nt1;
+  const int tx = r.tile / (nt2 * nt1);
+  const int x = tx * TX + lane / TY, y = ty * TY + lane % TY, z = tz * kTileZ + i;
+  const C<T>* src = partial + (static_cast<int64_t>(r.first_slot) * kTileZ + i) * 64 + lane;
+  double sr = 0.0, si = 0.0;
+  int s = 0;
+  for (; s + 4 <= r.nslots; s += 4) {
+    C<T> v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = src[static_cast<int64_t>(s + j) * 64 * kTileZ];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      sr += static_cast<double>(v[j].re);
+      si += static_cast<double>(v[j].im);
+    }
+  }
+  for (; s < r.nslots; ++s) {
+    const C<T> v = src[static_cast<int64_t>(s) * 64 * kTileZ];
+    sr += static_cast<double>(v.re);
+    si += static_cast<double>(v.im);
+  }
+  F[(static_cast<int64_t>(x) * nf1 + y) * nf2 + z] = C<T>{static_cast<T>(sr), static_cast<T>(si)};
+}
+
+// ------------------------------------------------------------------ drivers
+// ev (nullable): events recorded on s at the start (ev[0]) and after each stage:
+// 1 last-axis FFT (pad), 2 axis-1 FFT, 3 axis-0 FFT, 4 interpolation, 5 spread,
+// 6 spread reduce, 7 axis-0 FFT, 8 axis-1 FFT, 9 last-axis FFT (truncate).
+#define DDI_REC(i)                                 \
+  do {                                             \
+    if (ev) DDI_CHECK(hipEventRecord(ev[(i)], s)); \
+  } while (0)
+
+// Forward transform of the padded, deconvolved density onto the fine grid (pruned:
+// only lines that can hold non-zeros are transformed).
+template <typename T, int SIGN>
+static hipError_t type2_fft(DevicePlan& P, const T* rho, hipStream_t s, hipEvent_t* ev) {
+  const HostTables& H = P.H;
+  C<T>* F = reinterpret_cast<C<T>*>(P.fine);
+  const C<T>* tw2 = reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[2])]);
+  DDI_CHECK((launch_contig<T, SIGN, R2C_PAD>(H.nf[2], rho, F, H.N[0], H.N[1], H.nf[0], H.nf[1], H.N[2],
+                                             P.deconv[0], P.deconv[1], P.deconv[2], tw2, s)));
+  DDI_REC(1);
+  DDI_CHECK((launch_strided<T, SIGN>(H.nf[1], F, 1, H.nf[0], H.nf[1], H.nf[2], H.N[0], 1, H.N[1], 1, 0,
+                                     reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[1])]), s)));
+  DDI_REC(2);
+  if (H.nf[0] > 1) {
+    DDI_CHECK((launch_strided<T, SIGN>(H.nf[0], F, 0, H.nf[0], H.nf[1], H.nf[2], H.nf[1], 0, H.N[0], 1, 0,
+                                       reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[0])]), s)));
+  }
+  DDI_REC(3);
+  return hipSuccess;
+}
+
+// Inverse transform of the spread grid, keeping only the modes of the compact grid.
+template <typename T, int SIGN>
+static hipError_t type1_fft(DevicePlan& P, T* phi, hipStream_t s, hipEvent_t* ev) {
+  const HostTables& H = P.H;
+  C<T>* F = reinterpret_cast<C<T>*>(P.fine);
+  if (H.nf[0] > 1) {
+    DDI_CHECK((launch_strided<T, SIGN>(H.nf[0], F, 0, H.nf[0], H.nf[1], H.nf[2], H.nf[1], 0, H.N[0], 0, 1,
+                                       reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[0])]), s)));
+  }
+  DDI_REC(7);
+  DDI_CHECK((launch_strided<T, SIGN>(H.nf[1], F, 1, H.nf[0], H.nf[1], H.nf[2], H.N[0], 1, H.N[1], 0, 1,
+                                     reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[1])]), s)));
+  DDI_REC(8);
+  const C<T>* tw2 = reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[2])]);
+  DDI_CHECK((launch_contig<T, SIGN, C2R_TRUNC>(H.nf[2], F, phi, H.N[0], H.N[1], H.nf[0], H.nf[1], H.N[2],
+                                               P.deconv[0], P.deconv[1], P.deconv[2], tw2, s)));
+  DDI_REC(9);
+  return hipSuccess;
+}
+
+template <typename T, int W0, int W, int IB>
+static hipError_t interp_w(DevicePlan& P, C<T>* out, const double* scale, double sscalar, hipStream_t s) {
+  const HostTables& H = P.H;
+  const int ng = static_cast<int>(H.interp_items.size());
+  if (ng > 0) {
+    constexpr int R = IB + W - 1;
+    constexpr int R0 = W0 == 1 ? 1 : IB + W0 - 1;
+    const size_t shm = static_cast<size_t>(R0) * R * R * sizeof(C<T>);
+    if (H.ib[1] != IB || H.ireg[1] != R || H.ireg[0] != R0) return hipErrorInvalidValue;
+    if (!P.interp_lds_ready) {
+      DDI_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_interp_lds<T, W0, W, IB>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shm)));
+      P.interp_lds_ready = true;
+    }
+    hipLaunchKernelGGL((k_interp_lds<T, W0, W, IB>), dim3(ng), dim3(256), shm, s,
+                       reinterpret_cast<const C<T>*>(P.fine), reinterpret_cast<const NodeRec<T>*>(P.nodes),
+                       P.interp_items, H.nf[0], H.nf[1], H.nf[2], scale, sscalar, out);
+    DDI_CHECK(hipGetLastError());
+  }
+  const int64_t nd = static_cast<int64_t>(H.interp_direct.size());
+  if (nd > 0) {
+    constexpr int per_block = 4 * InterpShape<W>::NS;
+    const int blocks = static_cast<int>((nd + per_block - 1) / per_block);
+    hipLaunchKernelGGL((k_interp<T, W0, W>), dim3(blocks), dim3(256), 0, s, reinterpret_cast<const C<T>*>(P.fine),
+                       reinterpret_cast<const NodeRec<T>*>(P.nodes), P.interp_direct, nd, H.nf[0], H.nf[1], H.nf[2],
+                       scale, sscalar, out);
+    DDI_CHECK(hipGetLastError());
+  }
+  return hipSuccess;
+}
+
+template <typename T, int W>
+static hipError_t interp_d(DevicePlan& P, C<T>* out, const double* scale, double sscalar, hipStream_t s) {
+  if (P.H.W[0] == 1) return interp_w<T, 1, W, 8>(P, out, scale, sscalar, s);
+  return interp_w<T, W, W, 4>(P, out, scale, sscalar, s);
+}
+
+template <typename T>
+static hipError_t interp(DevicePlan& P, C<T>* out, const double* scale, double sscalar, hipStream_t s) {
+  switch (P.H.w) {
+    case 2: return interp_d<T, 2>(P, out, scale, sscalar, s);
+    case 3: return interp_d<T, 3>(P, out, scale, sscalar, s);
+    case 4: return interp_d<T, 4>(P, out, scale, sscalar, s);
+    case 5: return interp_d<T, 5>(P, out, scale, sscalar, s);
+    case 6: return interp_d<T, 6>(P, out, scale, sscalar, s);
+    case 7: return interp_d<T, 7>(P, out, scale, sscalar, s);
+    case 8: return interp_d<T, 8>(P, out, scale, sscalar, s);
+    case 9: return interp_d<T, 9>(P, out, scale, sscalar, s);
+    case 10: return interp_d<T, 10>(P, out, scale, sscalar, s);
+    case 11: return interp_d<T, 11>(P, out, scale, sscalar, s);
+    case 12: return interp_d<T, 12>(P, out, scale, sscalar, s);
+    case 13: return interp_d<T, 13>(P, out, scale, sscalar, s);
+    case 14: return interp_d<T, 14>(P, out, scale, sscalar, s);
+    case 15: return interp_d<T, 15>(P, out, scale, sscalar, s);
+    case 16: return interp_d<T, 16>(P, out, scale, sscalar, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T, int TX, int TY>
+static hipError_t spread_t(DevicePlan& P, const C<T>* g, hipStream_t s, hipEvent_t* ev) {
+  const HostTables& H = P.H;
+  C<T>* F = reinterpret_cast<C<T>*>(P.fine);
+  const int nitems = static_cast<int>(H.items.size());
+  constexpr bool kahan = sizeof(T) == 4;
+  hipLaunchKernelGGL((k_spread<T, kahan, TX, TY>), dim3(nitems), dim3(64), 0, s, F,
+                     reinterpret_cast<C<T>*>(P.partial), reinterpret_cast<const NodeRec<T>*>(P.nodes), g, P.list,
+                     P.items, H.nf[0], H.nf[1], H.nf[2], H.ntiles[1], H.ntiles[2], H.W[0], H.W[1], H.W[2]);
+  DDI_CHECK(hipGetLastError());
+  DDI_REC(5);
+  if (!H.reduces.empty()) {
+    hipLaunchKernelGGL((k_spread_reduce<T, TX, TY>), dim3(static_cast<int>(H.reduces.size())), dim3(64 * kTileZ), 0,
+                       s, F, reinterpret_cast<const C<T>*>(P.partial), P.reduces, H.nf[1], H.nf[2], H.ntiles[1],
+                       H.ntiles[2]);
+    DDI_CHECK(hipGetLastError());
+  }
+  DDI_REC(6);
+  return hipSuccess;
+}
+
+template <typename T>
+static hipError_t spread(DevicePlan& P, const C<T>* g, hipStream_t s, hipEvent_t* ev) {
+  if (P.H.tile[0] == 8 && P.H.tile[1] == 8) return spread_t<T, 8, 8>(P, g, s, ev);
+  if (P.H.tile[0] == 1 && P.H.tile[1] == 64) return spread_t<T, 1, 64>(P, g, s, ev);
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t run_type2(DevicePlan& P, const T* rho, Complex<T>* out, const double* scale, double cscalar, int sign,
+                     hipStream_t s, hipEvent_t* ev) {
+  DDI_REC(0);
+  if (sign < 0) DDI_CHECK((type2_fft<T, -1>(P, rho, s, ev)));
+  else DDI_CHECK((type2_fft<T, +1>(P, rho, s, ev)));
+  DDI_CHECK((interp<T>(P, out, scale, cscalar, s)));
+  DDI_REC(4);
+  return hipSuccess;
+}
+
+template <typename T>
+hipError_t run_type1(DevicePlan& P, const Complex<T>* g, T* phi, int sign, hipStream_t s, hipEvent_t* ev) {
+  DDI_CHECK(spread<T>(P, g, s, ev));
+  if (sign > 0) return type1_fft<T, +1>(P, phi, s, ev);
+  return type1_fft<T, -1>(P, phi, s, ev);
+}
+
+// Forward (sign = +1: exp(-ikx) to the nodes, exp(+ikx) back) or literal adjoint (sign = -1).
+template <typename T>
+hipError_t run_apply(DevicePlan& P, const T* rho, T* phi, int sign, hipStream_t s, hipEvent_t* ev) {
+  C<T>* g = reinterpret_cast<C<T>*>(P.gnodes);
+  DDI_CHECK(run_type2<T>(P, rho, g, P.c_scaled, 1.0, -sign, s, ev));
+  return run_type1<T>(P, g, phi, sign, s, ev);
+}
+
+template hipError_t run_type2<double>(DevicePlan&, const double*, Complex<double>*, const double*, double, int,
+                                      hipStream_t, hipEvent_t*);
+template hipError_t run_type2<float>(DevicePlan&, const float*, Complex<float>*, const double*, double, int,
+                                     hipStream_t, hipEvent_t*);
+template hipError_t run_type1<double>(DevicePlan&, const Complex<double>*, double*, int, hipStream_t, hipEvent_t*);
+template hipError_t run_type1<float>(DevicePlan&, const Complex<float>*, float*, int, hipStream_t, hipEvent_t*);
+template hipError_t run_apply<double>(DevicePlan&, const double*, double*, int, hipStream_t, hipEvent_t*);
+template hipError_t run_apply<float>(DevicePlan&, const float*, float*, int, hipStream_t, hipEvent_t*);
+
+}  // namespace ddi

@@ -71,6 +71,33 @@ double es_fourier(double m, int nf, int w, double beta, const std::vector<double
   return static_cast<double>(2.0L * 0.5L * half * acc);
 }
 
+// Dispatch order for work items that are listed in spatial order: cut the list into
+// kXcd contiguous segments of about equal work and interleave them, so that with the
+// round-robin assignment of workgroups to XCDs (workgroup b runs on XCD b mod kXcd)
+// each XCD works through one compact region of the grid and its L2 sees the reuse.
+// Shorter segments are padded with `pad` items, which the kernels skip.
+template <typename Item, typename Work>
+std::vector<Item> xcd_order(const std::vector<Item>& items, Work work, const Item& pad) {
+  constexpr int kXcd = 8;
+  if (items.size() < 2 * kXcd) return items;
+  double total = 0.0;
+  for (const Item& it : items) total += work(it);
+  std::vector<size_t> cut(kXcd + 1, items.size());
+  cut[0] = 0;
+  double acc = 0.0;
+  int seg = 1;
+  for (size_t i = 0; i < items.size() && seg < kXcd; ++i) {
+    acc += work(items[i]);
+    if (acc >= total * seg / kXcd) cut[seg++] = i + 1;
+  }
+  size_t longest = 0;
+  for (int x = 0; x < kXcd; ++x) longest = std::max(longest, cut[x + 1] - cut[x]);
+  std::vector<Item> out(longest * kXcd, pad);
+  for (int x = 0; x < kXcd; ++x)
+    for (size_t j = 0; j < cut[x + 1] - cut[x]; ++j) out[j * kXcd + x] = items[cut[x] + j];
+  return out;
+}
+
 }  // namespace
 
 std::vector<double> twiddle_table(int n) {
@@ -127,6 +154,10 @@ std::string build_tables(const ddi_params& p, HostTables& t, int* status) {
   for (int a = 0; a < 3; ++a) t.cell *= (a >= off ? t.h[a] : 1.0);
   if (d == 3) { t.tile[0] = 8; t.tile[1] = 8; t.tile[2] = kTileZ; }
   else { t.tile[0] = 1; t.tile[1] = 64; t.tile[2] = kTileZ; }
+  for (int a = 0; a < 3; ++a) {
+    t.ib[a] = t.N[a] == 1 ? 1 : (d == 3 ? 4 : 8);
+    t.ireg[a] = t.ib[a] + t.W[a] - 1;
+  }
   for (int a = 0; a < 3; ++a) t.ntiles[a] = t.nf[a] / t.tile[a];
 
   // ---------------------------------------------------------------- quadrature
@@ -234,11 +265,12 @@ std::string build_tables(const ddi_params& p, HostTables& t, int* status) {
         if (l0 < 0) l0 += t.nf[a];
       }
       l0_nat[3 * q + a] = l0;
-      tile_id = tile_id * t.ntiles[a] + l0 / t.tile[a];
+      tile_id = tile_id * (t.nf[a] / t.ib[a]) + l0 / t.ib[a];
     }
     home[q] = tile_id;
   }
-  // sort nodes by the tile that holds the start of their support (stable)
+  // sort nodes by the interpolation group (the block of ib^3 cells holding the start of
+  // their support); stable, so natural order is kept inside a group
   std::vector<int64_t> perm(M);
   std::iota(perm.begin(), perm.end(), 0);
   std::stable_sort(perm.begin(), perm.end(), [&](int64_t x, int64_t y) { return home[x] < home[y]; });
@@ -257,6 +289,40 @@ std::string build_tables(const ddi_params& p, HostTables& t, int* status) {
     t.c[s] = c_nat[q];
     std::memcpy(&t.wts[static_cast<size_t>(s) * 3 * kWMax], &w_nat[static_cast<size_t>(q) * 3 * kWMax],
                 sizeof(double) * 3 * kWMax);
+  }
+
+  // ---------------------------------------------------------------- interpolation groups
+  {
+    std::vector<int64_t> key(M);
+    for (int64_t s2 = 0; s2 < M; ++s2) key[s2] = home[perm[s2]];
+    const int gmin = 6, chunk_i = 256;
+    t.interp_items.clear();
+    t.interp_direct.clear();
+    for (int64_t b = 0; b < M;) {
+      int64_t e = b;
+      while (e < M && key[e] == key[b]) ++e;
+      if (e - b >= gmin) {
+        int org[3];
+        for (int a = 0; a < 3; ++a) org[a] = (t.l0[3 * b + a] / t.ib[a]) * t.ib[a];
+        for (int64_t c = b; c < e; c += chunk_i) {
+          InterpItem it;
+          it.start = static_cast<int32_t>(c);
+          it.count = static_cast<int32_t>(std::min<int64_t>(chunk_i, e - c));
+          it.org[0] = org[0];
+          it.org[1] = org[1];
+          it.org[2] = org[2];
+          t.interp_items.push_back(it);
+        }
+      } else {
+        for (int64_t c = b; c < e; ++c) t.interp_direct.push_back(static_cast<int32_t>(c));
+      }
+      b = e;
+    }
+    const double wcube = static_cast<double>(t.W[0]) * t.W[1] * t.W[2];
+    const double rcube = static_cast<double>(t.ireg[0]) * t.ireg[1] * t.ireg[2];
+    InterpItem pad{};
+    t.interp_items = xcd_order(t.interp_items, [&](const InterpItem& it) { return it.count * wcube + rcube; },
+                               pad);
   }
 
   // ---------------------------------------------------------------- deconvolution 1/phihat
@@ -326,9 +392,9 @@ std::string build_tables(const ddi_params& p, HostTables& t, int* status) {
       }
     }
   }
-  // heaviest items first so that the long ones start early
-  std::stable_sort(t.items.begin(), t.items.end(),
-                   [](const SpreadItem& x, const SpreadItem& y) { return x.count > y.count; });
+  // items are in tile order; each XCD gets one contiguous region of equal work
+  t.items = xcd_order(t.items, [](const SpreadItem& it) { return 16.0 + it.count; },
+                      SpreadItem{-1, 0, 0, -1});
   t.nslots = slot;
   *status = DDI_OK;
   return "";
