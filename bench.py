@@ -126,6 +126,71 @@ def cpu_baseline(wl, rho, dip, M_eff, target_s):
                       f"evals/s = (sample/M_eff)/time"}
 
 
+def other_workloads(args, torch, np, I, DDIPlan):
+    """The remaining workloads, each timed on its own plan: quasi-2D 512^2 FP64 (c3_512),
+    3D 256^3 mixed (c4_256) and the 128^3 ground-state gradient flow (c5_gf, 200 steps)."""
+    from paper_1504_02897_amd.gf import ground_state
+    res = {}
+    reps = max(5, args.steps // 2)
+
+    name = "c3_512"
+    wl = I.WORKLOADS[name]
+    d = I.mixture_workload(name, seed=args.seed)
+    print(f"[bench] {name}", file=sys.stderr, flush=True)
+    p = DDIPlan(2, wl["n"], wl["L"], dip_n=tuple(d["dip_n"]), quad=wl["quad"], tol=wl["tol"], prec="fp64")
+    r = torch.from_numpy(d["rho"]).cuda()
+    o = torch.empty_like(r)
+    ms = time_steps(lambda: p.apply(r, out=o), reps, 3, torch)
+    st = p.profile(r, reps=3)
+    res["c3_2d_fp64"] = {"workload": "c3_512: quasi-2D DDI, 512^2 on [-16,16)^2, mixture of 1-6 lumps + 10% "
+                                     "random-phase noise, n tilted 45 deg from z, polar 128x256",
+                         "value": round(1000.0 / ms, 2), "unit": "evals/s", "ms_per_step": round(ms, 4),
+                         "m_eff": p.m_eff, "stages_ms": {k: round(v, 4) for k, v in st.items()}}
+    del p, r, o
+
+    name = "c4_256"
+    wl = I.WORKLOADS[name]
+    d = I.mixture_workload(name, seed=args.seed)
+    print(f"[bench] {name}", file=sys.stderr, flush=True)
+    p = DDIPlan(3, wl["n"], wl["L"], dip_n=tuple(d["dip_n"]), quad=wl["quad"], tol=wl["tol"], prec="mixed")
+    r = torch.from_numpy(d["rho"]).cuda().float()
+    o = torch.empty_like(r)
+    a = torch.empty_like(r)
+    ms = time_steps(lambda: p.apply(r, out=o), reps, 3, torch)
+    fa = time_steps(lambda: (p.apply(r, out=o), p.apply_adjoint(o, out=a)), max(3, reps // 2), 2, torch)
+    st = p.profile(r, reps=3)
+    model = stage_model(p, 4, 8)
+    dom = max(st, key=st.get)
+    res["c4_256_mixed"] = {"workload": "c4_256: 3D DDI mixed precision, 256^3 on [-16,16)^3, seeded mixture, "
+                                       "quadrature 128x64x128",
+                           "value": round(1000.0 / ms, 2), "unit": "evals/s", "ms_per_step": round(ms, 4),
+                           "fwd_adj_ms": round(fa, 4), "m_eff": p.m_eff,
+                           "roofline": roofline_of(dom, st[dom], model, FP32_PEAK_TFLOPS),
+                           "stages_ms": {k: round(v, 4) for k, v in st.items()}}
+    del p, r, o, a
+
+    name = "c5_gf"
+    wl = I.WORKLOADS[name]
+    print(f"[bench] {name}", file=sys.stderr, flush=True)
+    p = DDIPlan(3, wl["n"], wl["L"], dip_n=(0.0, 0.0, 1.0), quad=wl["quad"], tol=wl["tol"], prec="fp64")
+    psi0 = torch.from_numpy(I.gf_initial(wl["n"], wl["L"], wl["gamma"])).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    psi, hist = ground_state(p, psi0, wl["beta"], wl["lam"], wl["gamma"], dt=wl["dt"], steps=wl["steps"],
+                             energy_every=50)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    E, G = p.energy_grad(psi, wl["beta"], wl["lam"], wl["gamma"], grad=True)
+    fa = time_steps(lambda: p.energy_grad(psi, wl["beta"], wl["lam"], wl["gamma"], grad=True), 5, 1, torch)
+    res["c5_gradient_flow"] = {
+        "workload": "c5_gf: 3D dipolar GPE ground state by gradient flow, 128^3 on [-8,8)^3, "
+                    "V=(x^2+y^2+25z^2)/2, beta=200, lambda=150, n=z, dt=0.01, 200 steps, FP64",
+        "steps": wl["steps"], "ms_per_step": round(1000.0 * el / wl["steps"], 3),
+        "energy_history": [[h[0], round(h[5], 8), round(h[7], 6)] for h in hist],
+        "E_final": [float(v) for v in E], "energy_grad_ms": round(fa, 3)}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,6 +200,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--profile-reps", type=int, default=10)
+    ap.add_argument("--headline-only", action="store_true",
+                    help="skip the 2D, 256^3 mixed and gradient-flow workloads")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see the sharding notes); "
@@ -190,6 +257,12 @@ def main():
     roof32 = roofline_of(dom32, stages32[dom32], model32, FP32_PEAK_TFLOPS)
     roof32["stages_ms"] = {k: round(v, 4) for k, v in stages32.items()}
 
+    width32 = p32.info["width"]
+    del p32, rho32, phi32, adj32
+    extra = {}
+    if not args.headline_only:
+        extra = other_workloads(args, torch, np, I, DDIPlan)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle, bounded sample)", file=sys.stderr, flush=True)
@@ -215,10 +288,11 @@ def main():
         "fwd_adj_ms": round(fa64, 4),
         "mixed": {"value": round(1000.0 / ms32, 3), "unit": "evals/s", "ms_per_step": round(ms32, 4),
                   "fwd_adj_ms": round(fa32, 4), "rel_linf_vs_fp64": err_mixed,
-                  "kernel_width": p32.info["width"], "roofline": roof32},
+                  "kernel_width": width32, "roofline": roof32},
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    line.update(extra)
     print(json.dumps(line), flush=True)
 
 

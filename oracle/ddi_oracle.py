@@ -425,3 +425,17 @@ def rel_linf(approx, exact) -> float:
     """max |Phi - Phi_h| / max |Phi|."""
     exact = np.asarray(exact)
     return float(np.max(np.abs(np.asarray(approx) - exact)) / np.max(np.abs(exact)))
+
+
+def nodes_to_points(g: np.ndarray, prob: DDIProblem, k: np.ndarray, points: np.ndarray,
+                    block: int = 65536) -> np.ndarray:
+    """Phi at selected grid points: Phi_l = Re sum_q g_q exp(+i k_q . x_l) for each index row of
+    ``points`` (shape (P, d)); the same sum as nodes_to_grid, one point at a time."""
+    xs = prob.axes()
+    X = np.stack([xs[a][points[:, a]] for a in range(prob.dim)], axis=1)      # (P, d)
+    out = np.zeros(points.shape[0])
+    for s in range(0, k.shape[0], block):
+        arg = X @ k[s:s + block].T                                              # (P, B)
+        gb = g[s:s + block]
+        out += np.cos(arg) @ gb.real - np.sin(arg) @ gb.imag
+    return out

@@ -1,0 +1,211 @@
+"""Parity at the workloads' full sizes, in the launch configuration the benchmark times,
+on outputs the oracle can produce one by one (stored values from tests/golden/make_golden.py
+or sampled sums computed here), plus invariants that hold at any size and edge cases."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import ddi_oracle as O
+from paper_1504_02897_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1504_02897_amd.ddi import DDIError, DDIPlan  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+DEV = "cuda:0"
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def golden(name):
+    with open(os.path.join(GOLDEN, f"{name}_seed0.json")) as f:
+        return json.load(f)
+
+
+def workload_plan(name, dip, prec=None):
+    wl = I.WORKLOADS[name]
+    prec = prec or wl["prec"]
+    return DDIPlan(wl["dim"], wl["n"], wl["L"], dip_n=tuple(dip), quad=wl["quad"], tol=wl["tol"], prec=prec)
+
+
+def plan_rows(plan, node_index):
+    """Positions in plan order of the nodes listed by (radial, polar, azimuthal) index."""
+    idx, _, _ = plan.nodes()
+    key = {tuple(t): i for i, t in enumerate(idx.tolist())}
+    return np.array([key[tuple(t)] for t in node_index])
+
+
+@pytest.mark.parametrize("name", ["c2_128", "c3_512"])
+def test_full_apply_matches_stored_oracle(name):
+    say(f"case: {name} full-size apply fp64 vs stored oracle samples")
+    gd = golden(name)
+    d = I.mixture_workload(name, seed=0)
+    plan = workload_plan(name, gd["dip_n"])
+    phi = plan.apply(torch.from_numpy(d["rho"]).to(DEV)).cpu().numpy()
+    pts = np.array(gd["points"])
+    got = np.array([phi[tuple(p)] for p in pts])
+    err = float(np.max(np.abs(got - np.array(gd["phi"])))) / gd["phi_absmax"]
+    say(f"  sampled rel Linf = {err:.3e}; max|Phi| {np.max(np.abs(phi)):.15e} vs {gd['phi_absmax']:.15e}")
+    assert err < 1e-12
+    assert abs(np.max(np.abs(phi)) - gd["phi_absmax"]) < 1e-12 * gd["phi_absmax"]
+    assert abs(np.linalg.norm(phi.ravel()) - gd["phi_l2"]) < 1e-12 * gd["phi_l2"]
+
+
+@pytest.mark.parametrize("name,tol", [("c2_128", 1e-13), ("c3_512", 1e-13), ("c4_256", 1e-6)])
+def test_full_type2_matches_stored_oracle(name, tol):
+    say(f"case: {name} full-size type-2 at sampled nodes")
+    gd = golden(name)
+    d = I.mixture_workload(name, seed=0)
+    plan = workload_plan(name, gd["dip_n"])
+    assert plan.m_eff == gd["m_eff"]
+    rho = torch.from_numpy(d["rho"]).to(DEV, plan.real_dtype)
+    rh = plan.type2(rho).cpu().numpy().astype(np.complex128)
+    rows = plan_rows(plan, gd["node_index"])
+    ref = np.array([complex(a, b) for a, b in gd["rhohat"]])
+    err = float(np.max(np.abs(rh[rows] - ref))) / gd["rhohat0"]
+    say(f"  rel err (to rhohat(0)) = {err:.3e}")
+    assert err < tol
+
+
+def test_c4_mixed_type1_sampled_points():
+    say("case: c4_256 mixed type-1, random node values, oracle at sampled points")
+    name = "c4_256"
+    wl = I.WORKLOADS[name]
+    d = I.mixture_workload(name, seed=0)
+    plan = workload_plan(name, d["dip_n"])
+    prob = O.DDIProblem(dim=3, n=wl["n"], L=wl["L"], dip_n=tuple(d["dip_n"]), n_rad=wl["quad"][0],
+                        n_pol=wl["quad"][1], n_azi=wl["quad"][2])
+    quad, c = O.ddi_nodes(prob)
+    idx, _, _ = plan.nodes()
+    key = {tuple(t): i for i, t in enumerate(quad.index.tolist())}
+    rows = np.array([key[tuple(t)] for t in idx.tolist()])
+    rng = np.random.default_rng(17)
+    g = (c[rows] * (rng.standard_normal(plan.m_eff) + 1j * rng.standard_normal(plan.m_eff))).astype(np.complex64)
+    phi = plan.type1(torch.from_numpy(g).to(DEV)).cpu().numpy().astype(np.float64)
+    pts = np.stack([rng.integers(0, 256, size=24) for _ in range(3)], axis=1)
+    ref = O.nodes_to_points(g.astype(np.complex128), prob, quad.k[rows], pts)
+    got = np.array([phi[tuple(p)] for p in pts])
+    scale = float(np.max(np.abs(phi)))
+    err = float(np.max(np.abs(got - ref))) / scale
+    say(f"  rel err (to max|Phi|) = {err:.3e}")
+    assert err < 1e-6
+
+
+@pytest.mark.parametrize("name", ["c2_128", "c4_256"])
+def test_full_size_trace_identity(name):
+    """sum over the three coordinate axes of Phi[n = m = e_i] vanishes node by node (any size)."""
+    say(f"case: {name} trace identity")
+    d = I.mixture_workload(name, seed=0)
+    wl = I.WORKLOADS[name]
+    rho = torch.from_numpy(d["rho"]).to(DEV, torch.float32 if wl["prec"] == "mixed" else torch.float64)
+    tot = None
+    ref = 0.0
+    for e in np.eye(3):
+        p = workload_plan(name, e)
+        phi = p.apply(rho).double()
+        ref = max(ref, float(phi.abs().max()))
+        tot = phi if tot is None else tot + phi
+        del p
+    err = float(tot.abs().max()) / ref
+    say(f"  |sum_i Phi_i| / max|Phi| = {err:.3e}")
+    assert err < (1e-12 if wl["prec"] == "fp64" else 1e-6)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 1e-6)])
+def test_full_size_symmetry(prec, tol):
+    """<A a, b> = <a, A b> at 128^3 in the benchmark's configuration."""
+    say(f"case: c2_128 symmetry {prec}")
+    d = I.mixture_workload("c2_128", seed=0)
+    plan = workload_plan("c2_128", d["dip_n"], prec=prec)
+    a = torch.from_numpy(d["rho"]).to(DEV, plan.real_dtype)
+    b = torch.from_numpy(np.abs(I.random_field(3, (128, 128, 128)))).to(DEV, plan.real_dtype)
+    Aa, Ab = plan.apply(a).double(), plan.apply(b).double()
+    lhs = float(torch.sum(Aa * b.double()))
+    rhs = float(torch.sum(a.double() * Ab))
+    scale = math.sqrt(float(torch.sum(Aa * Aa)) * float(torch.sum(b.double() ** 2)))
+    say(f"  |<Aa,b>-<a,Ab>| / scale = {abs(lhs - rhs) / scale:.3e}")
+    assert abs(lhs - rhs) < tol * scale
+
+
+def test_maximum_grid_size_512():
+    """The largest supported 3D grid (512^3, fine grid 1024^3): runs, finite, trace identity."""
+    say("case: 512^3 fp64 maximum size")
+    n, L = (512, 512, 512), (16.0,) * 3
+    x = torch.linspace(-16, 16 - 32 / 512, 512, dtype=torch.float64, device=DEV)
+    rho = torch.exp(-(x[:, None, None] ** 2 + x[None, :, None] ** 2 / 2 + x[None, None, :] ** 2 / 3))
+    tot = None
+    ref = 0.0
+    for e in np.eye(3):
+        p = DDIPlan(3, n, L, dip_n=tuple(e), quad=(16, 8, 16), tol=1e-13)
+        phi = p.apply(rho)
+        assert bool(torch.isfinite(phi).all())
+        ref = max(ref, float(phi.abs().max()))
+        tot = phi if tot is None else tot + phi
+        del p, phi
+    assert float(tot.abs().max()) < 1e-12 * ref
+
+
+def test_zero_density_gives_zero():
+    say("case: zero input")
+    p = DDIPlan(3, (32, 32, 32), (8.0,) * 3, dip_n=(0.6, 0, 0.8), quad=(16, 8, 16))
+    phi = p.apply(torch.zeros((32, 32, 32), dtype=torch.float64, device=DEV))
+    assert float(phi.abs().max()) == 0.0
+
+
+def test_no_node_inside_box_is_an_error():
+    """kmax far below the grid's Nyquist limit keeps every node; a tiny box with huge kmax too -
+    but a plan whose nodes all fall outside the mask must be rejected."""
+    with pytest.raises(DDIError):
+        DDIPlan(3, (16, 16, 16), (8.0,) * 3, quad=(2, 2, 4), kmax=1e6)
+
+
+def test_gradient_flow_32_matches_oracle_and_lowers_energy():
+    """Config-5 physics on a 32^3 grid (R18 reading): three GF steps vs the oracle, energy decreases."""
+    say("case: gradient flow 32^3")
+    wl = I.WORKLOADS["c5_gf"]
+    n, L = (32, 32, 32), wl["L"]
+    p = DDIPlan(3, n, L, dip_n=(0, 0, 1.0), quad=(32, 16, 32), tol=1e-13)
+    prob = O.DDIProblem(dim=3, n=n, L=L, dip_n=(0, 0, 1.0), n_rad=32, n_pol=16, n_azi=32)
+    gp = O.GPEParams(beta=wl["beta"], lam=wl["lam"], gamma=wl["gamma"])
+    psi = I.gf_initial(n, L, wl["gamma"])
+    x = torch.from_numpy(psi).to(DEV)
+    E0, _ = p.energy_grad(x, gp.beta, gp.lam, gp.gamma, grad=False)
+    ref = psi
+    for _ in range(3):
+        x = p.gf_step(x, gp.beta, gp.lam, gp.gamma, dt=wl["dt"], n_inner=1)
+        ref = O.gf_step(ref, prob, gp, dt=wl["dt"], n_inner=1)
+    err = float(np.max(np.abs(x.cpu().numpy() - ref)) / np.max(np.abs(ref)))
+    say(f"  3-step rel Linf vs oracle = {err:.3e}")
+    assert err < 1e-12
+    E3, _ = p.energy_grad(x, gp.beta, gp.lam, gp.gamma, grad=False)
+    assert E3[4] < E0[4]
+
+
+def test_gpe_gradient_fd_32():
+    """Central differences with delta = 1e-6 on 32^3 (config 5 reading), FP64."""
+    say("case: GPE gradient FD 32^3")
+    wl = I.WORKLOADS["c5_gf"]
+    n, L = (32, 32, 32), wl["L"]
+    p = DDIPlan(3, n, L, dip_n=(0, 0, 1.0), quad=(32, 16, 32), tol=1e-13)
+    lumps, _ = I.mixture_lumps(0, 3, (1, 4), centre=2.0, widths=(0.8, 1.6))
+    psi, _ = I.normalise(I.lumps_on_grid(lumps, n, L), n, L)
+    x = torch.from_numpy(psi).to(DEV)
+    E, G = p.energy_grad(x, wl["beta"], wl["lam"], wl["gamma"])
+    v = I.random_field(1, n, complex_=True)
+    dlt = 1e-6
+    Ep, _ = p.energy_grad(torch.from_numpy(psi + dlt * v).to(DEV), wl["beta"], wl["lam"], wl["gamma"], grad=False)
+    Em, _ = p.energy_grad(torch.from_numpy(psi - dlt * v).to(DEV), wl["beta"], wl["lam"], wl["gamma"], grad=False)
+    fd = (Ep[4] - Em[4]) / (2 * dlt)
+    an = 2.0 * float(np.real(np.vdot(v, G.cpu().numpy())))
+    say(f"  FD {fd:.12e} analytic {an:.12e}")
+    assert abs(fd - an) < 1e-6 * abs(an)
