@@ -30,7 +30,8 @@ def hipcc():
 
 
 def common_flags():
-    return ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
+    extra = os.environ.get("DDI_EXTRA_FLAGS", "").split()
+    return [*extra, "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-I", os.path.join(ROOT, "include")]
 

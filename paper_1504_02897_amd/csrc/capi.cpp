@@ -2,6 +2,7 @@
 // uploads, argument checks and dispatch on the precision.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -43,9 +44,13 @@ hipError_t upload(X** dst, const X* src, size_t count, hipStream_t s, int64_t& b
 }
 
 void free_plan(ddi::DevicePlan& P) {
-  void* ptrs[] = {P.nodes, P.c_scaled, P.deconv[0], P.deconv[1], P.deconv[2], P.list, P.items, P.reduces,
-                  P.interp_items, P.interp_direct,
+  void* ptrs[] = {P.nodes, P.c_scaled, P.c_half, P.deconv[0], P.deconv[1], P.deconv[2],
                   P.fine, P.gnodes, P.partial, P.gpe_rho, P.gpe_phi, P.gpe_phit, P.gpe_c1, P.gpe_c2, P.gpe_red};
+  for (auto& d : P.dsched) {
+    void* sp[] = {d.list, d.items, d.reduces, d.interp_items, d.interp_direct};
+    for (void* p : sp)
+      if (p) (void)hipFree(p);
+  }
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   for (void* p : P.twiddles)
@@ -69,16 +74,23 @@ ddi_status build_device(ddi::DevicePlan& P, hipStream_t s, std::vector<ddi::Node
   ddi::NodeRec<T>* dn = nullptr;
   HIP_TRY(upload(&dn, recs.data(), recs.size(), s, bytes), "upload node table");
   P.nodes = dn;
-  std::vector<double> cs(H.M);
+  std::vector<double> cs(H.M), cs_half(H.M);
   for (int64_t q = 0; q < H.M; ++q) cs[q] = H.c[q] * H.cell;
   HIP_TRY(upload(&P.c_scaled, cs.data(), cs.size(), s, bytes), "upload weights");
+  for (int64_t q = 0; q < H.M; ++q) cs_half[q] = H.half_factor[q] * H.c[q] * H.cell;
+  HIP_TRY(upload(&P.c_half, cs_half.data(), cs_half.size(), s, bytes), "upload weights");
   for (int a = 0; a < 3; ++a)
     HIP_TRY(upload(&P.deconv[a], H.deconv[a].data(), H.deconv[a].size(), s, bytes), "upload deconvolution");
-  HIP_TRY(upload(&P.list, H.list.data(), H.list.size(), s, bytes), "upload spread lists");
-  HIP_TRY(upload(&P.items, H.items.data(), H.items.size(), s, bytes), "upload spread items");
-  HIP_TRY(upload(&P.reduces, H.reduces.data(), H.reduces.size(), s, bytes), "upload spread reduces");
-  HIP_TRY(upload(&P.interp_items, H.interp_items.data(), H.interp_items.size(), s, bytes), "upload interp groups");
-  HIP_TRY(upload(&P.interp_direct, H.interp_direct.data(), H.interp_direct.size(), s, bytes), "upload interp list");
+  for (int w = 0; w < 2; ++w) {
+    const ddi::Schedule& S = H.sched[w];
+    auto& D = P.dsched[w];
+    HIP_TRY(upload(&D.list, S.list.data(), S.list.size(), s, bytes), "upload spread lists");
+    HIP_TRY(upload(&D.items, S.items.data(), S.items.size(), s, bytes), "upload spread items");
+    HIP_TRY(upload(&D.reduces, S.reduces.data(), S.reduces.size(), s, bytes), "upload spread reduces");
+    HIP_TRY(upload(&D.interp_items, S.interp_items.data(), S.interp_items.size(), s, bytes), "upload interp groups");
+    HIP_TRY(upload(&D.interp_direct, S.interp_direct.data(), S.interp_direct.size(), s, bytes),
+            "upload interp list");
+  }
   // twiddles for every FFT length used: fine grid sizes and the unpadded sizes
   tws.assign(11, {});
   for (int a = 0; a < 3; ++a) {
@@ -100,8 +112,9 @@ ddi_status build_device(ddi::DevicePlan& P, hipStream_t s, std::vector<ddi::Node
   bytes += nfine * static_cast<int64_t>(sizeof(ddi::Complex<T>));
   HIP_TRY(hipMalloc(&P.gnodes, H.M * sizeof(ddi::Complex<T>)), "allocate node values");
   bytes += H.M * static_cast<int64_t>(sizeof(ddi::Complex<T>));
-  if (H.nslots > 0) {
-    const int64_t pbytes = static_cast<int64_t>(H.nslots) * 64 * ddi::kTileZ * sizeof(ddi::Complex<T>);
+  const int32_t nslots = std::max(H.sched[0].nslots, H.sched[1].nslots);
+  if (nslots > 0) {
+    const int64_t pbytes = static_cast<int64_t>(nslots) * 64 * ddi::kTileZ * sizeof(ddi::Complex<T>);
     HIP_TRY(hipMalloc(&P.partial, pbytes), "allocate spread partial tiles");
     bytes += pbytes;
   }
@@ -174,9 +187,11 @@ ddi_status ddi_plan(const ddi_params* params, void* stream, ddi_plan_t* out) {
     const size_t elem = P.mixed ? 2 * sizeof(float) : 2 * sizeof(double);
     const size_t need = static_cast<size_t>(P.H.ireg[0]) * P.H.ireg[1] * P.H.ireg[2] * elem;
     if (need > static_cast<size_t>(max_lds)) {
-      for (const ddi::InterpItem& it : P.H.interp_items)
-        for (int32_t c = 0; c < it.count; ++c) P.H.interp_direct.push_back(it.start + c);
-      P.H.interp_items.clear();
+      for (ddi::Schedule& S : P.H.sched) {
+        for (const ddi::InterpItem& it : S.interp_items)
+          for (int32_t c = 0; c < it.count; ++c) S.interp_direct.push_back(it.start + c);
+        S.interp_items.clear();
+      }
     }
   }
   ddi_status ds;
@@ -218,8 +233,8 @@ ddi_status ddi_plan_info(ddi_plan_t plan, ddi_plan_info_t* info) {
   info->width = H.w;
   info->es_beta = H.es_beta;
   info->kmax = H.kmax;
-  info->spread_items = static_cast<int64_t>(H.items.size());
-  info->spread_entries = static_cast<int64_t>(H.list.size());
+  info->spread_items = static_cast<int64_t>(H.sched[ddi::kHalf].items.size());
+  info->spread_entries = static_cast<int64_t>(H.sched[ddi::kHalf].list.size());
   info->workspace_bytes = plan->P.workspace_bytes;
   return DDI_OK;
 }
@@ -302,10 +317,10 @@ ddi_status ddi_type2(ddi_plan_t plan, const void* rho_dev, void* rhohat_dev, voi
   ddi::DevicePlan& P = plan->P;
   hipError_t e;
   if (P.mixed)
-    e = ddi::run_type2<float>(P, static_cast<const float*>(rho_dev), static_cast<ddi::Complex<float>*>(rhohat_dev),
+    e = ddi::run_type2<float>(P, ddi::kAll, static_cast<const float*>(rho_dev), static_cast<ddi::Complex<float>*>(rhohat_dev),
                               nullptr, P.H.cell, -1, s, nullptr);
   else
-    e = ddi::run_type2<double>(P, static_cast<const double*>(rho_dev), static_cast<ddi::Complex<double>*>(rhohat_dev),
+    e = ddi::run_type2<double>(P, ddi::kAll, static_cast<const double*>(rho_dev), static_cast<ddi::Complex<double>*>(rhohat_dev),
                                nullptr, P.H.cell, -1, s, nullptr);
   if (e != hipSuccess) return hip_fail(e, "ddi_type2 launch");
   return DDI_OK;
@@ -317,8 +332,8 @@ ddi_status ddi_type1(ddi_plan_t plan, const void* g_dev, void* phi_dev, void* st
   if (!g_dev || !phi_dev) return fail(DDI_EINVAL, "NULL buffer");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   ddi::DevicePlan& P = plan->P;
-  hipError_t e = P.mixed ? ddi::run_type1<float>(P, static_cast<const ddi::Complex<float>*>(g_dev), static_cast<float*>(phi_dev), +1, s, nullptr)
-                         : ddi::run_type1<double>(P, static_cast<const ddi::Complex<double>*>(g_dev), static_cast<double*>(phi_dev), +1, s, nullptr);
+  hipError_t e = P.mixed ? ddi::run_type1<float>(P, ddi::kAll, static_cast<const ddi::Complex<float>*>(g_dev), static_cast<float*>(phi_dev), +1, s, nullptr)
+                         : ddi::run_type1<double>(P, ddi::kAll, static_cast<const ddi::Complex<double>*>(g_dev), static_cast<double*>(phi_dev), +1, s, nullptr);
   if (e != hipSuccess) return hip_fail(e, "ddi_type1 launch");
   return DDI_OK;
 }

@@ -13,6 +13,26 @@ namespace ddi {
 
 constexpr int kWMax = 16;          // largest kernel width
 constexpr int kTileZ = 8;          // spread tile extent along the last axis (registers per lane)
+#ifndef DDI_INTERP_BLOCK3
+#define DDI_INTERP_BLOCK3 4
+#endif
+#ifndef DDI_INTERP_MIN_GROUP
+#define DDI_INTERP_MIN_GROUP 6
+#endif
+// interpolation groups: block of cells per axis (3D) and smallest group staged in LDS
+constexpr int kInterpBlock3 = DDI_INTERP_BLOCK3;
+constexpr int kInterpMinGroup = DDI_INTERP_MIN_GROUP;
+#ifndef DDI_SPREAD_BATCH
+#define DDI_SPREAD_BATCH 64
+#endif
+// spread: nodes staged in LDS per batch (LDS per wave ~ batch * 26 values)
+constexpr int kSpreadBatch = DDI_SPREAD_BATCH;
+#ifndef DDI_SPREAD_XCD_ORDER
+#define DDI_SPREAD_XCD_ORDER 0
+#endif
+#ifndef DDI_SPREAD_UNROLL
+#define DDI_SPREAD_UNROLL 4
+#endif
 
 // One quadrature node as seen by the spread / interpolation kernels: the first
 // fine-grid index of its support on each axis (already reduced mod n_fine) and
@@ -50,6 +70,21 @@ struct ReduceItem {
   int32_t pad;
 };
 
+// Interpolation and spread work lists over one subset of the nodes.
+struct Schedule {
+  std::vector<InterpItem> interp_items;   // grouped nodes (LDS-staged region)
+  std::vector<int32_t> interp_direct;     // nodes interpolated straight from the grid
+  std::vector<int32_t> list;              // spread: node indices per tile, concatenated
+  std::vector<SpreadItem> items;
+  std::vector<ReduceItem> reduces;
+  int32_t nslots = 0;
+};
+
+// The two node subsets a plan schedules.  kAll: every node (the type-2 / type-1 entry
+// points, whose node values are arbitrary).  kHalf: one node of each +-k pair (the
+// operator on real grids, where the pair's terms are complex conjugates).
+enum { kAll = 0, kHalf = 1 };
+
 // Host-side tables built by build_tables() (all FP64).
 struct HostTables {
   int dim = 3;
@@ -75,14 +110,10 @@ struct HostTables {
   std::vector<int32_t> l0;     // [M][3]
   std::vector<double> wts;     // [M][3][kWMax]
   std::vector<double> deconv[3];   // 1/phihat per compact index, length N[a]
-  // spread schedule
-  std::vector<int32_t> list;       // node indices per tile, concatenated
-  std::vector<SpreadItem> items;
-  std::vector<ReduceItem> reduces;
-  int32_t nslots = 0;
-  // interpolation schedule
-  std::vector<InterpItem> interp_items;   // grouped nodes (LDS-staged region)
-  std::vector<int32_t> interp_direct;     // nodes interpolated straight from the grid
+  // per node: 2 for the kept member of a complete +-k pair, 1 for a node whose partner
+  // was masked out, 0 for the partner that is not kept in the half set
+  std::vector<double> half_factor;
+  Schedule sched[2];
 };
 
 // Builds every host table of a plan.  Returns an empty string on success or an error message.
@@ -121,11 +152,14 @@ struct DevicePlan {
   void* nodes = nullptr;         // NodeRec<T>[M]
   double* c_scaled = nullptr;    // c_q * prod(h) [M]
   double* deconv[3] = {nullptr, nullptr, nullptr};
-  int32_t* list = nullptr;
-  SpreadItem* items = nullptr;
-  ReduceItem* reduces = nullptr;
-  InterpItem* interp_items = nullptr;
-  int32_t* interp_direct = nullptr;
+  double* c_half = nullptr;       // half_factor * c_q * prod(h) [M]
+  struct DevSchedule {
+    int32_t* list = nullptr;
+    SpreadItem* items = nullptr;
+    ReduceItem* reduces = nullptr;
+    InterpItem* interp_items = nullptr;
+    int32_t* interp_direct = nullptr;
+  } dsched[2];
   bool interp_lds_ready = false;
   void* twiddles[11] = {};       // per log2(n): Complex<T>[n]
   // workspace
@@ -145,10 +179,11 @@ struct DevicePlan {
 
 // Kernel launchers (kernels.hip), templated on the real type.
 template <typename T>
-hipError_t run_type2(DevicePlan& P, const T* rho, Complex<T>* out, const double* scale, double cscalar,
-                     int sign, hipStream_t s, hipEvent_t* ev);
+hipError_t run_type2(DevicePlan& P, int which, const T* rho, Complex<T>* out, const double* scale,
+                     double cscalar, int sign, hipStream_t s, hipEvent_t* ev);
 template <typename T>
-hipError_t run_type1(DevicePlan& P, const Complex<T>* g, T* phi, int sign, hipStream_t s, hipEvent_t* ev);
+hipError_t run_type1(DevicePlan& P, int which, const Complex<T>* g, T* phi, int sign, hipStream_t s,
+                     hipEvent_t* ev);
 template <typename T>
 hipError_t run_apply(DevicePlan& P, const T* rho, T* phi, int sign, hipStream_t s, hipEvent_t* ev);
 constexpr int kStages = 9;

@@ -169,8 +169,8 @@ __device__ __forceinline__ int cmap(int k, int n, int nc) { return k < nc - nc /
 // z per workgroup.  The other non-z axis runs over n_o lines (compact when
 // o_compact: index o -> fine index fmap(o, d_o, n_o)).  in_compact / out_compact:
 // only the N_c active positions of the line are read (rest zero) / written.
-template <typename T, int N, int SIGN>
-__global__ void __launch_bounds__(256) k_fft_strided(C<T>* __restrict__ F, int axis, int d0, int d1, int d2,
+template <typename T, int N, int SIGN, int MAXT>
+__global__ void __launch_bounds__(MAXT) k_fft_strided(C<T>* __restrict__ F, int axis, int d0, int d1, int d2,
                                                      int n_o, int o_compact, int nc_axis, int in_compact,
                                                      int out_compact, const C<T>* __restrict__ tw, int B) {
   extern __shared__ unsigned char smem_raw[];
@@ -287,12 +287,21 @@ template <typename T, int N, int SIGN>
 static hipError_t launch_strided_n(C<T>* F, int axis, int d0, int d1, int d2, int n_o, int o_compact, int nc,
                                    int in_c, int out_c, const C<T>* tw, hipStream_t s) {
   constexpr int TL = N / RadixPlan<N>::R1;
+  // lines per workgroup: at least 256 threads, and row segments of >= 128 B along the
+  // contiguous axis (coalescing) as far as 1024 threads and 64 KB of LDS allow
   int B = 256 / TL;
+  while (B * static_cast<int>(sizeof(C<T>)) < 128 && 2 * B * TL <= 1024 &&
+         static_cast<size_t>(2 * B) * N * sizeof(C<T>) <= 65536)
+    B *= 2;
   while (B > d2) B >>= 1;
   const size_t shm = static_cast<size_t>(B) * N * sizeof(C<T>);
   const int blocks = n_o * (d2 / B);
-  hipLaunchKernelGGL((k_fft_strided<T, N, SIGN>), dim3(blocks), dim3(B * TL), shm, s, F, axis, d0, d1, d2, n_o,
-                     o_compact, nc, in_c, out_c, tw, B);
+  if (B * TL <= 256)
+    hipLaunchKernelGGL((k_fft_strided<T, N, SIGN, 256>), dim3(blocks), dim3(B * TL), shm, s, F, axis, d0, d1, d2,
+                       n_o, o_compact, nc, in_c, out_c, tw, B);
+  else
+    hipLaunchKernelGGL((k_fft_strided<T, N, SIGN, 1024>), dim3(blocks), dim3(B * TL), shm, s, F, axis, d0, d1, d2,
+                       n_o, o_compact, nc, in_c, out_c, tw, B);
   return hipGetLastError();
 }
 

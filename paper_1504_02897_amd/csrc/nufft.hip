@@ -34,8 +34,8 @@ struct InterpShape {
 // Grouped nodes: the workgroup stages the support region of its group (IB + W - 1 cells
 // per axis; 1 on the unused axis of a 2D grid) in LDS once.  Region strides are
 // compile-time, so every LDS read uses an immediate offset from one base address.
-template <typename T, int W0, int W, int IB>
-__global__ void __launch_bounds__(256) k_interp_lds(const C<T>* __restrict__ F, const NodeRec<T>* __restrict__ nodes,
+template <typename T, int W0, int W, int IB, int NT>
+__global__ void __launch_bounds__(NT) k_interp_lds(const C<T>* __restrict__ F, const NodeRec<T>* __restrict__ nodes,
                                                     const InterpItem* __restrict__ items, int nf0, int nf1, int nf2,
                                                     const double* __restrict__ scale, double sscalar,
                                                     C<T>* __restrict__ out) {
@@ -47,7 +47,7 @@ __global__ void __launch_bounds__(256) k_interp_lds(const C<T>* __restrict__ F, 
   // items are pre-ordered so that round-robin dispatch gives each XCD one region of equal work
   const InterpItem it = items[blockIdx.x];
   if (it.count == 0) return;                 // padding item
-  for (int i = threadIdx.x; i < R0 * R * R; i += 256) {
+  for (int i = threadIdx.x; i < R0 * R * R; i += NT) {
     const int rz = i % R;
     const int t = i / R;
     const int ry = t % R, rx = t / R;
@@ -64,7 +64,7 @@ __global__ void __launch_bounds__(256) k_interp_lds(const C<T>* __restrict__ F, 
   const int wv = threadIdx.x >> 6;
   const int sl = lane / SL, u = lane % SL;
   const bool zin = u < W;
-  for (int n0 = wv * NS; n0 < it.count; n0 += 4 * NS) {
+  for (int n0 = wv * NS; n0 < it.count; n0 += (NT / 64) * NS) {
     const int n = n0 + sl;
     const bool valid = n < it.count;
     const int64_t q = static_cast<int64_t>(it.start) + (valid ? n : it.count - 1);
@@ -181,10 +181,11 @@ __global__ void __launch_bounds__(64) k_spread(C<T>* __restrict__ F, C<T>* __res
                                                int nt1, int nt2, int w0, int w1, int w2) {
   static_assert(TX * TY == 64, "one wave per tile");
   constexpr int TZ = kTileZ;
-  __shared__ T sx[64][TX];
-  __shared__ T sy[64][TY];
-  __shared__ T sz[64][TZ];
-  __shared__ C<T> sg[64];
+  constexpr int NB = kSpreadBatch;           // nodes staged per batch
+  __shared__ T sx[NB][TX];
+  __shared__ T sy[NB][TY];
+  __shared__ T sz[NB][TZ];
+  __shared__ C<T> sg[NB];
   const int lane = threadIdx.x;
   const SpreadItem it = items[blockIdx.x];
   if (it.tile < 0) return;                   // padding item
@@ -200,8 +201,8 @@ __global__ void __launch_bounds__(64) k_spread(C<T>* __restrict__ F, C<T>* __res
     acc[i] = C<T>{0, 0};
     cmp[i] = C<T>{0, 0};
   }
-  for (int base = 0; base < it.count; base += 64) {
-    const int n = it.count - base < 64 ? it.count - base : 64;
+  for (int base = 0; base < it.count; base += NB) {
+    const int n = it.count - base < NB ? it.count - base : NB;
     // stage the weights of up to 64 nodes restricted to this tile (one node per lane);
     // loads are unconditional (index clamped into the record) so that all are in flight
     if (lane < n) {
@@ -246,6 +247,7 @@ __global__ void __launch_bounds__(64) k_spread(C<T>* __restrict__ F, C<T>* __res
       sg[lane] = gq;
     }
     __syncthreads();
+#pragma unroll DDI_SPREAD_UNROLL
     for (int e = 0; e < n; ++e) {
       const C<T> gq = sg[e];
       T wz[TZ];
@@ -369,30 +371,34 @@ static hipError_t type1_fft(DevicePlan& P, T* phi, hipStream_t s, hipEvent_t* ev
 }
 
 template <typename T, int W0, int W, int IB>
-static hipError_t interp_w(DevicePlan& P, C<T>* out, const double* scale, double sscalar, hipStream_t s) {
+static hipError_t interp_w(DevicePlan& P, int which, C<T>* out, const double* scale, double sscalar,
+                           hipStream_t s) {
   const HostTables& H = P.H;
-  const int ng = static_cast<int>(H.interp_items.size());
+  const Schedule& S = H.sched[which];
+  const DevicePlan::DevSchedule& D = P.dsched[which];
+  const int ng = static_cast<int>(S.interp_items.size());
   if (ng > 0) {
     constexpr int R = IB + W - 1;
     constexpr int R0 = W0 == 1 ? 1 : IB + W0 - 1;
+    constexpr int NT = 512;   // 8 waves: the LDS region limits residency to two workgroups per CU
     const size_t shm = static_cast<size_t>(R0) * R * R * sizeof(C<T>);
     if (H.ib[1] != IB || H.ireg[1] != R || H.ireg[0] != R0) return hipErrorInvalidValue;
     if (!P.interp_lds_ready) {
-      DDI_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_interp_lds<T, W0, W, IB>),
+      DDI_CHECK(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_interp_lds<T, W0, W, IB, NT>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(shm)));
       P.interp_lds_ready = true;
     }
-    hipLaunchKernelGGL((k_interp_lds<T, W0, W, IB>), dim3(ng), dim3(256), shm, s,
+    hipLaunchKernelGGL((k_interp_lds<T, W0, W, IB, NT>), dim3(ng), dim3(NT), shm, s,
                        reinterpret_cast<const C<T>*>(P.fine), reinterpret_cast<const NodeRec<T>*>(P.nodes),
-                       P.interp_items, H.nf[0], H.nf[1], H.nf[2], scale, sscalar, out);
+                       D.interp_items, H.nf[0], H.nf[1], H.nf[2], scale, sscalar, out);
     DDI_CHECK(hipGetLastError());
   }
-  const int64_t nd = static_cast<int64_t>(H.interp_direct.size());
+  const int64_t nd = static_cast<int64_t>(S.interp_direct.size());
   if (nd > 0) {
     constexpr int per_block = 4 * InterpShape<W>::NS;
     const int blocks = static_cast<int>((nd + per_block - 1) / per_block);
     hipLaunchKernelGGL((k_interp<T, W0, W>), dim3(blocks), dim3(256), 0, s, reinterpret_cast<const C<T>*>(P.fine),
-                       reinterpret_cast<const NodeRec<T>*>(P.nodes), P.interp_direct, nd, H.nf[0], H.nf[1], H.nf[2],
+                       reinterpret_cast<const NodeRec<T>*>(P.nodes), D.interp_direct, nd, H.nf[0], H.nf[1], H.nf[2],
                        scale, sscalar, out);
     DDI_CHECK(hipGetLastError());
   }
@@ -400,47 +406,51 @@ static hipError_t interp_w(DevicePlan& P, C<T>* out, const double* scale, double
 }
 
 template <typename T, int W>
-static hipError_t interp_d(DevicePlan& P, C<T>* out, const double* scale, double sscalar, hipStream_t s) {
-  if (P.H.W[0] == 1) return interp_w<T, 1, W, 8>(P, out, scale, sscalar, s);
-  return interp_w<T, W, W, 4>(P, out, scale, sscalar, s);
+static hipError_t interp_d(DevicePlan& P, int which, C<T>* out, const double* scale, double sscalar,
+                           hipStream_t s) {
+  if (P.H.W[0] == 1) return interp_w<T, 1, W, 8>(P, which, out, scale, sscalar, s);
+  return interp_w<T, W, W, kInterpBlock3>(P, which, out, scale, sscalar, s);
 }
 
 template <typename T>
-static hipError_t interp(DevicePlan& P, C<T>* out, const double* scale, double sscalar, hipStream_t s) {
+static hipError_t interp(DevicePlan& P, int which, C<T>* out, const double* scale, double sscalar,
+                         hipStream_t s) {
   switch (P.H.w) {
-    case 2: return interp_d<T, 2>(P, out, scale, sscalar, s);
-    case 3: return interp_d<T, 3>(P, out, scale, sscalar, s);
-    case 4: return interp_d<T, 4>(P, out, scale, sscalar, s);
-    case 5: return interp_d<T, 5>(P, out, scale, sscalar, s);
-    case 6: return interp_d<T, 6>(P, out, scale, sscalar, s);
-    case 7: return interp_d<T, 7>(P, out, scale, sscalar, s);
-    case 8: return interp_d<T, 8>(P, out, scale, sscalar, s);
-    case 9: return interp_d<T, 9>(P, out, scale, sscalar, s);
-    case 10: return interp_d<T, 10>(P, out, scale, sscalar, s);
-    case 11: return interp_d<T, 11>(P, out, scale, sscalar, s);
-    case 12: return interp_d<T, 12>(P, out, scale, sscalar, s);
-    case 13: return interp_d<T, 13>(P, out, scale, sscalar, s);
-    case 14: return interp_d<T, 14>(P, out, scale, sscalar, s);
-    case 15: return interp_d<T, 15>(P, out, scale, sscalar, s);
-    case 16: return interp_d<T, 16>(P, out, scale, sscalar, s);
+    case 2: return interp_d<T, 2>(P, which, out, scale, sscalar, s);
+    case 3: return interp_d<T, 3>(P, which, out, scale, sscalar, s);
+    case 4: return interp_d<T, 4>(P, which, out, scale, sscalar, s);
+    case 5: return interp_d<T, 5>(P, which, out, scale, sscalar, s);
+    case 6: return interp_d<T, 6>(P, which, out, scale, sscalar, s);
+    case 7: return interp_d<T, 7>(P, which, out, scale, sscalar, s);
+    case 8: return interp_d<T, 8>(P, which, out, scale, sscalar, s);
+    case 9: return interp_d<T, 9>(P, which, out, scale, sscalar, s);
+    case 10: return interp_d<T, 10>(P, which, out, scale, sscalar, s);
+    case 11: return interp_d<T, 11>(P, which, out, scale, sscalar, s);
+    case 12: return interp_d<T, 12>(P, which, out, scale, sscalar, s);
+    case 13: return interp_d<T, 13>(P, which, out, scale, sscalar, s);
+    case 14: return interp_d<T, 14>(P, which, out, scale, sscalar, s);
+    case 15: return interp_d<T, 15>(P, which, out, scale, sscalar, s);
+    case 16: return interp_d<T, 16>(P, which, out, scale, sscalar, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <typename T, int TX, int TY>
-static hipError_t spread_t(DevicePlan& P, const C<T>* g, hipStream_t s, hipEvent_t* ev) {
+static hipError_t spread_t(DevicePlan& P, int which, const C<T>* g, hipStream_t s, hipEvent_t* ev) {
   const HostTables& H = P.H;
+  const Schedule& S = H.sched[which];
+  const DevicePlan::DevSchedule& D = P.dsched[which];
   C<T>* F = reinterpret_cast<C<T>*>(P.fine);
-  const int nitems = static_cast<int>(H.items.size());
+  const int nitems = static_cast<int>(S.items.size());
   constexpr bool kahan = sizeof(T) == 4;
   hipLaunchKernelGGL((k_spread<T, kahan, TX, TY>), dim3(nitems), dim3(64), 0, s, F,
-                     reinterpret_cast<C<T>*>(P.partial), reinterpret_cast<const NodeRec<T>*>(P.nodes), g, P.list,
-                     P.items, H.nf[0], H.nf[1], H.nf[2], H.ntiles[1], H.ntiles[2], H.W[0], H.W[1], H.W[2]);
+                     reinterpret_cast<C<T>*>(P.partial), reinterpret_cast<const NodeRec<T>*>(P.nodes), g, D.list,
+                     D.items, H.nf[0], H.nf[1], H.nf[2], H.ntiles[1], H.ntiles[2], H.W[0], H.W[1], H.W[2]);
   DDI_CHECK(hipGetLastError());
   DDI_REC(5);
-  if (!H.reduces.empty()) {
-    hipLaunchKernelGGL((k_spread_reduce<T, TX, TY>), dim3(static_cast<int>(H.reduces.size())), dim3(64 * kTileZ), 0,
-                       s, F, reinterpret_cast<const C<T>*>(P.partial), P.reduces, H.nf[1], H.nf[2], H.ntiles[1],
+  if (!S.reduces.empty()) {
+    hipLaunchKernelGGL((k_spread_reduce<T, TX, TY>), dim3(static_cast<int>(S.reduces.size())), dim3(64 * kTileZ), 0,
+                       s, F, reinterpret_cast<const C<T>*>(P.partial), D.reduces, H.nf[1], H.nf[2], H.ntiles[1],
                        H.ntiles[2]);
     DDI_CHECK(hipGetLastError());
   }
@@ -449,44 +459,50 @@ static hipError_t spread_t(DevicePlan& P, const C<T>* g, hipStream_t s, hipEvent
 }
 
 template <typename T>
-static hipError_t spread(DevicePlan& P, const C<T>* g, hipStream_t s, hipEvent_t* ev) {
-  if (P.H.tile[0] == 8 && P.H.tile[1] == 8) return spread_t<T, 8, 8>(P, g, s, ev);
-  if (P.H.tile[0] == 1 && P.H.tile[1] == 64) return spread_t<T, 1, 64>(P, g, s, ev);
+static hipError_t spread(DevicePlan& P, int which, const C<T>* g, hipStream_t s, hipEvent_t* ev) {
+  if (P.H.tile[0] == 8 && P.H.tile[1] == 8) return spread_t<T, 8, 8>(P, which, g, s, ev);
+  if (P.H.tile[0] == 1 && P.H.tile[1] == 64) return spread_t<T, 1, 64>(P, which, g, s, ev);
   return hipErrorInvalidValue;
 }
 
 template <typename T>
-hipError_t run_type2(DevicePlan& P, const T* rho, Complex<T>* out, const double* scale, double cscalar, int sign,
-                     hipStream_t s, hipEvent_t* ev) {
+hipError_t run_type2(DevicePlan& P, int which, const T* rho, Complex<T>* out, const double* scale,
+                     double cscalar, int sign, hipStream_t s, hipEvent_t* ev) {
   DDI_REC(0);
   if (sign < 0) DDI_CHECK((type2_fft<T, -1>(P, rho, s, ev)));
   else DDI_CHECK((type2_fft<T, +1>(P, rho, s, ev)));
-  DDI_CHECK((interp<T>(P, out, scale, cscalar, s)));
+  DDI_CHECK((interp<T>(P, which, out, scale, cscalar, s)));
   DDI_REC(4);
   return hipSuccess;
 }
 
 template <typename T>
-hipError_t run_type1(DevicePlan& P, const Complex<T>* g, T* phi, int sign, hipStream_t s, hipEvent_t* ev) {
-  DDI_CHECK(spread<T>(P, g, s, ev));
+hipError_t run_type1(DevicePlan& P, int which, const Complex<T>* g, T* phi, int sign, hipStream_t s,
+                     hipEvent_t* ev) {
+  DDI_CHECK(spread<T>(P, which, g, s, ev));
   if (sign > 0) return type1_fft<T, +1>(P, phi, s, ev);
   return type1_fft<T, -1>(P, phi, s, ev);
 }
 
-// Forward (sign = +1: exp(-ikx) to the nodes, exp(+ikx) back) or literal adjoint (sign = -1).
+// Forward (sign = +1: exp(-ikx) to the nodes, exp(+ikx) back) or literal adjoint (sign = -1)
+// of the operator on real grids: one node of each +-k pair is interpolated and spread, its
+// weight carrying the factor 2 of the pair (the partner's term is the complex conjugate, and
+// only the real part is kept).
 template <typename T>
 hipError_t run_apply(DevicePlan& P, const T* rho, T* phi, int sign, hipStream_t s, hipEvent_t* ev) {
   C<T>* g = reinterpret_cast<C<T>*>(P.gnodes);
-  DDI_CHECK(run_type2<T>(P, rho, g, P.c_scaled, 1.0, -sign, s, ev));
-  return run_type1<T>(P, g, phi, sign, s, ev);
+  DDI_CHECK(run_type2<T>(P, kHalf, rho, g, P.c_half, 1.0, -sign, s, ev));
+  return run_type1<T>(P, kHalf, g, phi, sign, s, ev);
 }
 
-template hipError_t run_type2<double>(DevicePlan&, const double*, Complex<double>*, const double*, double, int,
-                                      hipStream_t, hipEvent_t*);
-template hipError_t run_type2<float>(DevicePlan&, const float*, Complex<float>*, const double*, double, int,
+template hipError_t run_type2<double>(DevicePlan&, int, const double*, Complex<double>*, const double*, double,
+                                      int, hipStream_t, hipEvent_t*);
+template hipError_t run_type2<float>(DevicePlan&, int, const float*, Complex<float>*, const double*, double, int,
                                      hipStream_t, hipEvent_t*);
-template hipError_t run_type1<double>(DevicePlan&, const Complex<double>*, double*, int, hipStream_t, hipEvent_t*);
-template hipError_t run_type1<float>(DevicePlan&, const Complex<float>*, float*, int, hipStream_t, hipEvent_t*);
+template hipError_t run_type1<double>(DevicePlan&, int, const Complex<double>*, double*, int, hipStream_t,
+                                      hipEvent_t*);
+template hipError_t run_type1<float>(DevicePlan&, int, const Complex<float>*, float*, int, hipStream_t,
+                                     hipEvent_t*);
 template hipError_t run_apply<double>(DevicePlan&, const double*, double*, int, hipStream_t, hipEvent_t*);
 template hipError_t run_apply<float>(DevicePlan&, const float*, float*, int, hipStream_t, hipEvent_t*);
 

@@ -98,6 +98,133 @@ std::vector<Item> xcd_order(const std::vector<Item>& items, Work work, const Ite
   return out;
 }
 
+// Morton (Z-order) key of a 3D block coordinate (each coordinate < 2^20): consecutive
+// keys stay compact in all three directions, so work that runs at the same time on one
+// XCD touches nearby grid rows and its L2 sees the reuse.
+uint64_t morton3(uint32_t x, uint32_t y, uint32_t z) {
+  auto spread = [](uint64_t v) {
+    v &= 0xFFFFF;
+    v = (v | (v << 32)) & 0x1F00000000FFFFull;
+    v = (v | (v << 16)) & 0x1F0000FF0000FFull;
+    v = (v | (v << 8)) & 0x100F00F00F00F00Full;
+    v = (v | (v << 4)) & 0x10C30C30C30C30C3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+  };
+  return (spread(x) << 2) | (spread(y) << 1) | spread(z);
+}
+
+}  // namespace
+
+namespace {
+
+// Interpolation work over the nodes selected by `used` (a prefix of every group block in
+// plan order): blocks with at least kInterpMinGroup selected nodes become LDS-staged items
+// (split into chunks), the other selected nodes are interpolated directly.
+template <typename Used>
+std::string build_interp_schedule(const HostTables& t, const std::vector<uint64_t>& key, Used used, Schedule& S) {
+  const int64_t M = t.M;
+  const int chunk_i = 256;
+  S.interp_items.clear();
+  S.interp_direct.clear();
+  for (int64_t b = 0; b < M;) {
+    int64_t e = b;
+    while (e < M && key[e] == key[b]) ++e;
+    int64_t ue = b;
+    while (ue < e && used(ue)) ++ue;
+    if (ue - b >= kInterpMinGroup) {
+      int org[3];
+      for (int a = 0; a < 3; ++a) org[a] = (t.l0[3 * b + a] / t.ib[a]) * t.ib[a];
+      for (int64_t c = b; c < ue; c += chunk_i) {
+        InterpItem it{};
+        it.start = static_cast<int32_t>(c);
+        it.count = static_cast<int32_t>(std::min<int64_t>(chunk_i, ue - c));
+        for (int a = 0; a < 3; ++a) it.org[a] = org[a];
+        S.interp_items.push_back(it);
+      }
+    } else {
+      for (int64_t c = b; c < ue; ++c) S.interp_direct.push_back(static_cast<int32_t>(c));
+    }
+    b = e;
+  }
+  // heaviest items first so that the long ones start early
+  std::stable_sort(S.interp_items.begin(), S.interp_items.end(),
+                   [](const InterpItem& x, const InterpItem& y) { return x.count > y.count; });
+  return "";
+}
+
+// Spread work over the nodes selected by `used`: for every tile of the fine grid, the
+// selected nodes whose support meets it (tiles in Morton order); tiles with more than
+// `chunk` nodes are split into chunks whose partial tiles are summed by reduce items.
+template <typename Used>
+std::string build_spread_schedule(const HostTables& t, const std::vector<int64_t>& tile_order, Used used,
+                                  Schedule& S) {
+  const int64_t M = t.M;
+  const int64_t ntile_total = static_cast<int64_t>(t.ntiles[0]) * t.ntiles[1] * t.ntiles[2];
+  auto touched = [&](int64_t s, int a, int* out) {
+    int cnt = 0;
+    for (int i = 0; i < t.W[a]; ++i) {
+      int pos = (t.l0[3 * s + a] + i) % t.nf[a];
+      int tl = pos / t.tile[a];
+      bool seen = false;
+      for (int j = 0; j < cnt; ++j) seen = seen || out[j] == tl;
+      if (!seen) out[cnt++] = tl;
+    }
+    return cnt;
+  };
+  std::vector<int64_t> count(ntile_total + 1, 0);
+  int tx[kWMax], ty[kWMax], tz[kWMax];
+  for (int pass = 0; pass < 2; ++pass) {
+    if (pass == 1) {
+      for (int64_t i = 0, run = 0; i <= ntile_total; ++i) { int64_t c = count[i]; count[i] = run; run += c; }
+      if (count[ntile_total] > (int64_t(1) << 31) - 1) return "spread schedule too large";
+      S.list.assign(count[ntile_total], 0);
+    }
+    std::vector<int64_t> fill;
+    if (pass == 1) fill.assign(count.begin(), count.end());
+    for (int64_t s = 0; s < M; ++s) {
+      if (!used(s)) continue;
+      int nx = touched(s, 0, tx), ny = touched(s, 1, ty), nz = touched(s, 2, tz);
+      for (int i = 0; i < nx; ++i)
+        for (int j = 0; j < ny; ++j)
+          for (int k = 0; k < nz; ++k) {
+            int64_t tid = (static_cast<int64_t>(tx[i]) * t.ntiles[1] + ty[j]) * t.ntiles[2] + tz[k];
+            if (pass == 0) count[tid]++;
+            else S.list[fill[tid]++] = static_cast<int32_t>(s);
+          }
+    }
+  }
+  const int chunk = 256;
+  S.items.clear();
+  S.reduces.clear();
+  int32_t slot = 0;
+  for (int64_t tord = 0; tord < ntile_total; ++tord) {
+    const int64_t tid = tile_order[tord];
+    int64_t beg = count[tid], n = count[tid + 1] - count[tid];
+    if (n <= chunk) {
+      S.items.push_back({static_cast<int32_t>(tid), static_cast<int32_t>(beg), static_cast<int32_t>(n), -1});
+    } else {
+      int nch = static_cast<int>((n + chunk - 1) / chunk);
+      S.reduces.push_back({static_cast<int32_t>(tid), slot, nch, 0});
+      for (int c = 0; c < nch; ++c) {
+        int64_t b = beg + static_cast<int64_t>(c) * chunk;
+        int64_t e = std::min(beg + n, b + chunk);
+        S.items.push_back({static_cast<int32_t>(tid), static_cast<int32_t>(b), static_cast<int32_t>(e - b), slot++});
+      }
+    }
+  }
+#if DDI_SPREAD_XCD_ORDER
+  // items are in tile order; each XCD gets one contiguous region of equal work
+  S.items = xcd_order(S.items, [](const SpreadItem& it) { return 16.0 + it.count; }, SpreadItem{-1, 0, 0, -1});
+#else
+  // heaviest items first so that the long ones start early
+  std::stable_sort(S.items.begin(), S.items.end(),
+                   [](const SpreadItem& x, const SpreadItem& y) { return x.count > y.count; });
+#endif
+  S.nslots = slot;
+  return "";
+}
+
 }  // namespace
 
 std::vector<double> twiddle_table(int n) {
@@ -155,7 +282,7 @@ std::string build_tables(const ddi_params& p, HostTables& t, int* status) {
   if (d == 3) { t.tile[0] = 8; t.tile[1] = 8; t.tile[2] = kTileZ; }
   else { t.tile[0] = 1; t.tile[1] = 64; t.tile[2] = kTileZ; }
   for (int a = 0; a < 3; ++a) {
-    t.ib[a] = t.N[a] == 1 ? 1 : (d == 3 ? 4 : 8);
+    t.ib[a] = t.N[a] == 1 ? 1 : (d == 3 ? kInterpBlock3 : 8);
     t.ireg[a] = t.ib[a] + t.W[a] - 1;
   }
   for (int a = 0; a < 3; ++a) t.ntiles[a] = t.nf[a] / t.tile[a];
@@ -247,9 +374,9 @@ std::string build_tables(const ddi_params& p, HostTables& t, int* status) {
   // ---------------------------------------------------------------- kernel geometry per node
   std::vector<int32_t> l0_nat(3 * M);
   std::vector<double> w_nat(static_cast<size_t>(3 * kWMax) * M, 0.0);
-  std::vector<int64_t> home(M);
+  std::vector<uint64_t> home(M);
   for (int64_t q = 0; q < M; ++q) {
-    int64_t tile_id = 0;
+    uint32_t hb[3] = {0, 0, 0};
     for (int a = 0; a < 3; ++a) {
       int l0 = 0;
       double* wq = &w_nat[(q * 3 + a) * kWMax];
@@ -265,20 +392,44 @@ std::string build_tables(const ddi_params& p, HostTables& t, int* status) {
         if (l0 < 0) l0 += t.nf[a];
       }
       l0_nat[3 * q + a] = l0;
-      tile_id = tile_id * (t.nf[a] / t.ib[a]) + l0 / t.ib[a];
+      hb[a] = static_cast<uint32_t>(l0 / t.ib[a]);
     }
-    home[q] = tile_id;
+    home[q] = morton3(hb[0], hb[1], hb[2]);
   }
+  // ---------------------------------------------------------------- +-k pairs
+  // The tensor rule is symmetric under k -> -k: (a, b, c) pairs with (a, n_pol-1-b,
+  // c + n_azi/2) (2D: (a, c + n_azi/2)), with equal weight and symbol.  On real grids the two
+  // terms of a pair are complex conjugates, so one member carries factor 2 and the other 0;
+  // a node whose partner the mask removed (or any node when n_azi is odd) keeps factor 1.
+  std::vector<double> hf_nat(M, 1.0);
+  if (nazi % 2 == 0) {
+    std::vector<int64_t> pos(static_cast<size_t>(p.n_rad) * npol * nazi, -1);
+    for (int64_t q = 0; q < M; ++q)
+      pos[(static_cast<size_t>(idx_nat[3 * q]) * npol + idx_nat[3 * q + 1]) * nazi + idx_nat[3 * q + 2]] = q;
+    for (int64_t q = 0; q < M; ++q) {
+      const int a = idx_nat[3 * q], b = idx_nat[3 * q + 1], c = idx_nat[3 * q + 2];
+      const int bp = d == 3 ? npol - 1 - b : 0;
+      const int cp = (c + nazi / 2) % nazi;
+      const int64_t pq = pos[(static_cast<size_t>(a) * npol + bp) * nazi + cp];
+      if (pq >= 0 && pq != q) hf_nat[q] = q < pq ? 2.0 : 0.0;
+    }
+  }
+
   // sort nodes by the interpolation group (the block of ib^3 cells holding the start of
-  // their support); stable, so natural order is kept inside a group
+  // their support), members of the half set first inside a group; stable otherwise
   std::vector<int64_t> perm(M);
   std::iota(perm.begin(), perm.end(), 0);
-  std::stable_sort(perm.begin(), perm.end(), [&](int64_t x, int64_t y) { return home[x] < home[y]; });
+  std::stable_sort(perm.begin(), perm.end(), [&](int64_t x, int64_t y) {
+    if (home[x] != home[y]) return home[x] < home[y];
+    return (hf_nat[x] > 0.0) > (hf_nat[y] > 0.0);
+  });
   t.index.resize(3 * M);
   t.k.resize(3 * M);
   t.c.resize(M);
+  t.half_factor.resize(M);
   t.l0.resize(3 * M);
   t.wts.resize(static_cast<size_t>(3 * kWMax) * M);
+  std::vector<uint64_t> key(M);
   for (int64_t s = 0; s < M; ++s) {
     int64_t q = perm[s];
     for (int a = 0; a < 3; ++a) {
@@ -287,42 +438,10 @@ std::string build_tables(const ddi_params& p, HostTables& t, int* status) {
       t.l0[3 * s + a] = l0_nat[3 * q + a];
     }
     t.c[s] = c_nat[q];
+    t.half_factor[s] = hf_nat[q];
+    key[s] = home[q];
     std::memcpy(&t.wts[static_cast<size_t>(s) * 3 * kWMax], &w_nat[static_cast<size_t>(q) * 3 * kWMax],
                 sizeof(double) * 3 * kWMax);
-  }
-
-  // ---------------------------------------------------------------- interpolation groups
-  {
-    std::vector<int64_t> key(M);
-    for (int64_t s2 = 0; s2 < M; ++s2) key[s2] = home[perm[s2]];
-    const int gmin = 6, chunk_i = 256;
-    t.interp_items.clear();
-    t.interp_direct.clear();
-    for (int64_t b = 0; b < M;) {
-      int64_t e = b;
-      while (e < M && key[e] == key[b]) ++e;
-      if (e - b >= gmin) {
-        int org[3];
-        for (int a = 0; a < 3; ++a) org[a] = (t.l0[3 * b + a] / t.ib[a]) * t.ib[a];
-        for (int64_t c = b; c < e; c += chunk_i) {
-          InterpItem it;
-          it.start = static_cast<int32_t>(c);
-          it.count = static_cast<int32_t>(std::min<int64_t>(chunk_i, e - c));
-          it.org[0] = org[0];
-          it.org[1] = org[1];
-          it.org[2] = org[2];
-          t.interp_items.push_back(it);
-        }
-      } else {
-        for (int64_t c = b; c < e; ++c) t.interp_direct.push_back(static_cast<int32_t>(c));
-      }
-      b = e;
-    }
-    const double wcube = static_cast<double>(t.W[0]) * t.W[1] * t.W[2];
-    const double rcube = static_cast<double>(t.ireg[0]) * t.ireg[1] * t.ireg[2];
-    InterpItem pad{};
-    t.interp_items = xcd_order(t.interp_items, [&](const InterpItem& it) { return it.count * wcube + rcube; },
-                               pad);
   }
 
   // ---------------------------------------------------------------- deconvolution 1/phihat
@@ -339,63 +458,29 @@ std::string build_tables(const ddi_params& p, HostTables& t, int* status) {
     }
   }
 
-  // ---------------------------------------------------------------- spread schedule
+  // ---------------------------------------------------------------- schedules
   const int64_t ntile_total = static_cast<int64_t>(t.ntiles[0]) * t.ntiles[1] * t.ntiles[2];
   if (ntile_total > (int64_t(1) << 30)) return "fine grid too large";
-  auto touched = [&](int64_t s, int a, int* out) {
-    int cnt = 0;
-    for (int i = 0; i < t.W[a]; ++i) {
-      int pos = (t.l0[3 * s + a] + i) % t.nf[a];
-      int tl = pos / t.tile[a];
-      bool seen = false;
-      for (int j = 0; j < cnt; ++j) seen = seen || out[j] == tl;
-      if (!seen) out[cnt++] = tl;
+  std::vector<int64_t> tile_order(ntile_total);
+  {
+    std::vector<uint64_t> tkey(ntile_total);
+    for (int64_t tid = 0; tid < ntile_total; ++tid) {
+      const uint32_t tz = static_cast<uint32_t>(tid % t.ntiles[2]);
+      const uint32_t ty = static_cast<uint32_t>((tid / t.ntiles[2]) % t.ntiles[1]);
+      const uint32_t tx = static_cast<uint32_t>(tid / (static_cast<int64_t>(t.ntiles[2]) * t.ntiles[1]));
+      tkey[tid] = morton3(tx, ty, tz);
+      tile_order[tid] = tid;
     }
-    return cnt;
-  };
-  std::vector<int64_t> count(ntile_total + 1, 0);
-  int tx[kWMax], ty[kWMax], tz[kWMax];
-  for (int pass = 0; pass < 2; ++pass) {
-    if (pass == 1) {
-      for (int64_t i = 0, run = 0; i <= ntile_total; ++i) { int64_t c = count[i]; count[i] = run; run += c; }
-      if (count[ntile_total] > (int64_t(1) << 31) - 1) return "spread schedule too large";
-      t.list.assign(count[ntile_total], 0);
-    }
-    std::vector<int64_t> fill;
-    if (pass == 1) fill.assign(count.begin(), count.end());
-    for (int64_t s = 0; s < M; ++s) {
-      int nx = touched(s, 0, tx), ny = touched(s, 1, ty), nz = touched(s, 2, tz);
-      for (int i = 0; i < nx; ++i)
-        for (int j = 0; j < ny; ++j)
-          for (int k = 0; k < nz; ++k) {
-            int64_t tid = (static_cast<int64_t>(tx[i]) * t.ntiles[1] + ty[j]) * t.ntiles[2] + tz[k];
-            if (pass == 0) count[tid]++;
-            else t.list[fill[tid]++] = static_cast<int32_t>(s);
-          }
-    }
+    std::stable_sort(tile_order.begin(), tile_order.end(),
+                     [&](int64_t x, int64_t y) { return tkey[x] < tkey[y]; });
   }
-  const int chunk = 256;
-  t.items.clear();
-  t.reduces.clear();
-  int32_t slot = 0;
-  for (int64_t tid = 0; tid < ntile_total; ++tid) {
-    int64_t beg = count[tid], n = count[tid + 1] - count[tid];
-    if (n <= chunk) {
-      t.items.push_back({static_cast<int32_t>(tid), static_cast<int32_t>(beg), static_cast<int32_t>(n), -1});
-    } else {
-      int nch = static_cast<int>((n + chunk - 1) / chunk);
-      t.reduces.push_back({static_cast<int32_t>(tid), slot, nch, 0});
-      for (int c = 0; c < nch; ++c) {
-        int64_t b = beg + static_cast<int64_t>(c) * chunk;
-        int64_t e = std::min(beg + n, b + chunk);
-        t.items.push_back({static_cast<int32_t>(tid), static_cast<int32_t>(b), static_cast<int32_t>(e - b), slot++});
-      }
-    }
+  for (int which = 0; which < 2; ++which) {
+    Schedule& S = t.sched[which];
+    auto used = [&](int64_t s2) { return which == kAll || t.half_factor[s2] > 0.0; };
+    std::string err = build_interp_schedule(t, key, used, S);
+    if (err.empty()) err = build_spread_schedule(t, tile_order, used, S);
+    if (!err.empty()) return err;
   }
-  // items are in tile order; each XCD gets one contiguous region of equal work
-  t.items = xcd_order(t.items, [](const SpreadItem& it) { return 16.0 + it.count; },
-                      SpreadItem{-1, 0, 0, -1});
-  t.nslots = slot;
   *status = DDI_OK;
   return "";
 }
