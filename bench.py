@@ -36,12 +36,13 @@ def stage_model(plan, real_bytes, cplx_bytes):
     the fine grid is read once, plus node records and node values.  Spread: the fine grid
     is written once, plus node records, node values and the tile lists.  Flops of
     interpolation/spread: 4 per (node, grid point) pair (a real weight times a complex
-    value accumulated), w^d pairs per node; of an FFT pass: 5 n log2 n per line.
+    value accumulated), w^d pairs per node, over the nodes the operator visits (one per
+    +-k pair); of an FFT pass: 5 n log2 n per line.
     """
     N = [1] * (3 - plan.dim) + list(plan.shape)
     nf = list(plan.info["n_fine"])
     w = plan.info["width"]
-    M = plan.m_eff
+    M = plan.info["m_half"]          # nodes the operator interpolates and spreads (one per +-k pair)
     d = plan.dim
     rec = 16 + 3 * 16 * real_bytes
     c = cplx_bytes
@@ -63,20 +64,56 @@ def stage_model(plan, real_bytes, cplx_bytes):
     return st
 
 
+KERNELS = {"fft_last_pad": "k_fft_contig (R2C_PAD)", "fft_axis1_t2": "k_fft_strided (axis 1)",
+           "fft_axis0_t2": "k_fft_strided (axis 0)", "interp": "k_interp_lds + k_interp",
+           "spread": "k_spread", "spread_reduce": "k_spread_reduce", "fft_axis0_t1": "k_fft_strided (axis 0)",
+           "fft_axis1_t1": "k_fft_strided (axis 1)", "fft_last_trunc": "k_fft_contig (C2R_TRUNC)"}
+
+
 def roofline_of(stage, ms, model, fp_peak_tflops):
+    """Roofline of one stage.  The binding roof is the larger of the two model times,
+    B/HBM-peak and F/VALU-peak; `frac` is that roof's time over the measured time."""
     b, f = model[stage]
     gbs = b / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
     tfl = f / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
     fr_h = gbs / HBM_PEAK_GBS
     fr_f = tfl / fp_peak_tflops
-    if stage in ("interp", "spread"):
+    common = {"traffic": None, "kernel": stage, "kernels": KERNELS.get(stage, stage), "kernel_ms": round(ms, 4),
+              "algorithmic_bytes": b, "algorithmic_flops": f}
+    if fr_f > fr_h:
         return {"bound": "alu", "achieved": round(tfl, 3), "peak": fp_peak_tflops, "unit": "TFLOP/s",
-                "frac": round(fr_f, 4), "traffic": None, "kernel": stage, "kernel_ms": round(ms, 4),
-                "hbm_GBs_algorithmic": round(gbs, 1), "hbm_frac": round(fr_h, 4),
-                "algorithmic_flops": f, "algorithmic_bytes": b}
+                "frac": round(fr_f, 4), **common, "hbm_GBs_algorithmic": round(gbs, 1), "hbm_frac": round(fr_h, 4)}
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(fr_h, 4), "traffic": None, "kernel": stage, "kernel_ms": round(ms, 4),
-            "algorithmic_bytes": b, "algorithmic_flops": f}
+            "frac": round(fr_h, 4), **common, "valu_TFLOPs_algorithmic": round(tfl, 3), "valu_frac": round(fr_f, 4)}
+
+
+def sources_digest():
+    """SHA-256 over the HIP/C++ sources of the library (sorted by name)."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1504_02897_amd", "csrc")
+    for n in sorted(os.listdir(d)):
+        if n.endswith((".hip", ".cpp", ".h")):
+            h.update(n.encode())
+            with open(os.path.join(d, n), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, prec, stage):
+    """HBM bytes per launch of a stage from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE, scaled by the copy calibration), or None when the kernels have changed since
+    the counters were taken or no summary covers the stage."""
+    path = os.path.join(ROOT, "profiles", f"{workload}_traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("sources_sha256") != sources_digest():
+        return None
+    e = t.get(prec, {}).get(stage)
+    return None if e is None else int(e["read_bytes"] + e["write_bytes"])
 
 
 def time_steps(fn, steps, warmup, torch):
@@ -251,10 +288,12 @@ def main():
     model64 = stage_model(p64, 8, 16)
     dom = max(stages64, key=stages64.get)
     roof = roofline_of(dom, stages64[dom], model64, FP64_PEAK_TFLOPS)
+    roof["traffic"] = measured_traffic("c2_128", "fp64", dom)
     roof["stages_ms"] = {k: round(v, 4) for k, v in stages64.items()}
     model32 = stage_model(p32, 4, 8)
     dom32 = max(stages32, key=stages32.get)
     roof32 = roofline_of(dom32, stages32[dom32], model32, FP32_PEAK_TFLOPS)
+    roof32["traffic"] = measured_traffic("c2_128", "mixed", dom32)
     roof32["stages_ms"] = {k: round(v, 4) for k, v in stages32.items()}
 
     width32 = p32.info["width"]
@@ -283,7 +322,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "c2_128: 3D DDI, 128^3 on [-12,12)^3, seeded Gaussian-mixture density "
                                f"(seed {args.seed}), random unit dipole axis, quadrature 96x48x96, tol 1e-13",
-                   "m_eff": p64.m_eff, "n_fine": list(p64.info["n_fine"]), "kernel_width": p64.info["width"],
+                   "m_eff": p64.m_eff, "m_half": p64.info["m_half"], "n_fine": list(p64.info["n_fine"]),
+                   "kernel_width": p64.info["width"],
                    "plan_s": round(plan_s, 2)},
         "fwd_adj_ms": round(fa64, 4),
         "mixed": {"value": round(1000.0 / ms32, 3), "unit": "evals/s", "ms_per_step": round(ms32, 4),

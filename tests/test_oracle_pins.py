@@ -291,6 +291,11 @@ def test_brute_force_long_double_rounding():
     ref = (cosm * (g * rr)).sum(axis=1) - (sinm * (g * ri)).sum(axis=1)
     err = np.max(np.abs(phi.ravel().astype(ld) - ref)) / np.max(np.abs(ref))
     assert err < 1e-14
+    # The pointwise type-1 sum at scattered grid points against the same brute-force values.
+    pts = np.array([[0, 0, 0], [3, 5, 7], [7, 1, 2], [4, 4, 4], [1, 6, 0]])
+    vals = O.nodes_to_points(c * O.rhohat(rho, p, quad.k), p, quad.k, pts)
+    flat = np.ravel_multi_index(tuple(pts.T), (N,) * 3)
+    assert np.max(np.abs(vals.astype(ld) - ref[flat])) / np.max(np.abs(ref)) < 1e-14
 
 
 # ---------------------------------------------------------------- energy and gradient
