@@ -45,9 +45,9 @@ hipError_t upload(X** dst, const X* src, size_t count, hipStream_t s, int64_t& b
 
 void free_plan(ddi::DevicePlan& P) {
   void* ptrs[] = {P.nodes, P.c_scaled, P.c_half, P.deconv[0], P.deconv[1], P.deconv[2],
-                  P.fine, P.gnodes, P.partial, P.gpe_rho, P.gpe_phi, P.gpe_phit, P.gpe_c1, P.gpe_c2, P.gpe_red};
+                  P.fine, P.gnodes, P.partial, P.ipartial, P.gpe_rho, P.gpe_phi, P.gpe_phit, P.gpe_c1, P.gpe_c2, P.gpe_red};
   for (auto& d : P.dsched) {
-    void* sp[] = {d.list, d.items, d.reduces, d.interp_items, d.interp_direct};
+    void* sp[] = {d.list, d.items, d.reduces, d.interp_items, d.interp_direct, d.gptr, d.gpos};
     for (void* p : sp)
       if (p) (void)hipFree(p);
   }
@@ -90,6 +90,10 @@ ddi_status build_device(ddi::DevicePlan& P, hipStream_t s, std::vector<ddi::Node
     HIP_TRY(upload(&D.interp_items, S.interp_items.data(), S.interp_items.size(), s, bytes), "upload interp groups");
     HIP_TRY(upload(&D.interp_direct, S.interp_direct.data(), S.interp_direct.size(), s, bytes),
             "upload interp list");
+    if (ddi::kInterpTile && sizeof(T) == 8 && H.tile[0] == 8) {
+      HIP_TRY(upload(&D.gptr, S.gptr.data(), S.gptr.size(), s, bytes), "upload interp gather");
+      HIP_TRY(upload(&D.gpos, S.gpos.data(), S.gpos.size(), s, bytes), "upload interp gather");
+    }
   }
   // twiddles for every FFT length used: fine grid sizes and the unpadded sizes
   tws.assign(11, {});
@@ -112,6 +116,12 @@ ddi_status build_device(ddi::DevicePlan& P, hipStream_t s, std::vector<ddi::Node
   bytes += nfine * static_cast<int64_t>(sizeof(ddi::Complex<T>));
   HIP_TRY(hipMalloc(&P.gnodes, H.M * sizeof(ddi::Complex<T>)), "allocate node values");
   bytes += H.M * static_cast<int64_t>(sizeof(ddi::Complex<T>));
+  const size_t nentries = std::max(H.sched[0].list.size(), H.sched[1].list.size());
+  if (nentries > 0 && ddi::kInterpTile && sizeof(T) == 8 && H.tile[0] == 8) {
+    const int64_t ib = static_cast<int64_t>(nentries) * sizeof(ddi::Complex<double>);
+    HIP_TRY(hipMalloc(&P.ipartial, ib), "allocate interpolation partial sums");
+    bytes += ib;
+  }
   const int32_t nslots = std::max(H.sched[0].nslots, H.sched[1].nslots);
   if (nslots > 0) {
     const int64_t pbytes = static_cast<int64_t>(nslots) * 64 * ddi::kTileZ * sizeof(ddi::Complex<T>);

@@ -33,6 +33,13 @@ constexpr int kSpreadBatch = DDI_SPREAD_BATCH;
 #ifndef DDI_SPREAD_UNROLL
 #define DDI_SPREAD_UNROLL 4
 #endif
+#ifndef DDI_INTERP_TILE
+#define DDI_INTERP_TILE 1
+#endif
+// FP64 interpolation in 3D: 1 = tile-owned (each fine-grid tile read once by a wave whose
+// lanes are (tile, node) entries; one partial per entry, gathered per node); 0 = node-owned
+// (LDS-staged groups plus direct reads of the fine grid), which FP32 and 2D always use
+constexpr bool kInterpTile = DDI_INTERP_TILE != 0;
 
 // One quadrature node as seen by the spread / interpolation kernels: the first
 // fine-grid index of its support on each axis (already reduced mod n_fine) and
@@ -78,6 +85,10 @@ struct Schedule {
   std::vector<SpreadItem> items;
   std::vector<ReduceItem> reduces;
   int32_t nslots = 0;
+  // tile-owned interpolation: one partial sum per list entry; the list positions of node q
+  // are gpos[gptr[q] .. gptr[q+1]) (increasing)
+  std::vector<int32_t> gptr;
+  std::vector<int32_t> gpos;
 };
 
 // The two node subsets a plan schedules.  kAll: every node (the type-2 / type-1 entry
@@ -159,6 +170,8 @@ struct DevicePlan {
     ReduceItem* reduces = nullptr;
     InterpItem* interp_items = nullptr;
     int32_t* interp_direct = nullptr;
+    int32_t* gptr = nullptr;
+    int32_t* gpos = nullptr;
   } dsched[2];
   bool interp_lds_ready = false;
   void* twiddles[11] = {};       // per log2(n): Complex<T>[n]
@@ -166,6 +179,7 @@ struct DevicePlan {
   void* fine = nullptr;          // Complex<T>[nf0*nf1*nf2]
   void* gnodes = nullptr;        // Complex<T>[M]
   void* partial = nullptr;       // Complex<T>[nslots][tile volume]
+  void* ipartial = nullptr;      // Complex<double>[spread entries]: interpolation partial sums
   int64_t workspace_bytes = 0;
   // GPE workspace (allocated on first use)
   void* gpe_rho = nullptr;       // T[N]

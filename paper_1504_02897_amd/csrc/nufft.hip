@@ -1,13 +1,17 @@
 // NUFFT halves of the DDI operator on gfx950 (Sec. 2.1, Eqs. DDI-Con, DDI-Trun1).
 //
 //   type-2 (grid -> nodes): deconvolve + zero-pad fused into the first FFT pass, pruned
-//     3-pass FFT on the oversampled grid, interpolation at the quadrature nodes (one wave per
-//     node, compile-time kernel width so that every load of a support row is in flight at
-//     once), weights g_q = c_q prod(h) rhohat_q fused into the epilogue.
-//   type-1 (nodes -> grid): tile-owned spread (a wave owns an 8 x 8 x 8 block of the fine grid
-//     in registers and sums the nodes whose support meets it, staged 64 at a time in LDS as
-//     tile-relative weight vectors; no atomics), hot tiles split into chunks whose partial tiles
-//     are summed in a fixed order by a reduce kernel; pruned 3-pass FFT with truncation,
+//     3-pass FFT on the oversampled grid, then interpolation at the quadrature nodes with the
+//     weights g_q = c_q prod(h) rhohat_q applied at the end.  FP64 interpolation in 3D is
+//     tile-owned: a wave stages one 8 x 8 x 8 tile of the fine grid in LDS, its lanes are the
+//     (tile, node) entries of that tile, and one partial per entry is summed per node by a
+//     gather kernel (the fine grid is read once).  Otherwise interpolation is node-owned: nodes
+//     grouped by home block read an LDS-staged support region, the rest read the grid
+//     directly (one wave per four nodes, compile-time kernel width).
+//   type-1 (nodes -> grid): tile-owned spread (a wave owns an 8 x 8 x 8 block of the fine
+//     grid in registers and sums the nodes whose support meets it, staged 64 at a time in LDS
+//     as tile-relative weight vectors; no atomics), hot tiles split into chunks whose partial
+//     tiles are summed in a fixed order by a reduce kernel; pruned 3-pass FFT with truncation,
 //     deconvolution and real part fused into the last pass.
 // Kernel weights are tabulated per node at plan time: nothing transcendental runs per apply.
 #include <hip/hip_runtime.h>
@@ -286,6 +290,108 @@ __global__ void __launch_bounds__(64) k_spread(C<T>* __restrict__ F, C<T>* __res
   }
 }
 
+// ------------------------------------------------------------------ tile-owned interpolation
+__device__ inline int mod_fine(int d, int n) { return d < 0 ? d + n : d; }
+
+// Lane-per-entry form (3D, 8 x 8 x kTileZ tiles): lane e of the wave takes entry e of the
+// tile (64 at a time), holds the node's kernel weights at the tile's positions in registers,
+// and walks the tile's 64 columns.  The tile is staged in LDS once per item (lane c loads
+// column c, coalesced along the last axis); every lane then reads the same column, so each
+// LDS read is a broadcast.  Per column a lane sums over z, then weights by y; per x row by x.
+// No cross-lane reduction.  Arithmetic in FP64.
+template <typename T>
+__global__ void __launch_bounds__(64) k_interp_col(const C<T>* __restrict__ F, const NodeRec<T>* __restrict__ nodes,
+                                                   const int32_t* __restrict__ list,
+                                                   const SpreadItem* __restrict__ items, int nf0, int nf1, int nf2,
+                                                   int nt1, int nt2, int w0, int w1, int w2,
+                                                   C<double>* __restrict__ part) {
+  constexpr int TX = 8, TY = 8, TZ = kTileZ;
+  const int lane = threadIdx.x;
+  const SpreadItem it = items[blockIdx.x];
+  if (it.tile < 0 || it.count == 0) return;  // padding item or empty tile
+  const int tz = it.tile % nt2;
+  const int ty = (it.tile / nt2) % nt1;
+  const int tx = it.tile / (nt2 * nt1);
+  const int x0 = tx * TX, y0 = ty * TY, z0 = tz * TZ;
+  __shared__ C<T> tileF[TX * TY * TZ];       // [x][y][z]
+  {
+    const C<T>* row = F + (static_cast<int64_t>(x0 + lane / TY) * nf1 + (y0 + lane % TY)) * nf2 + z0;
+    C<T> v[TZ];
+#pragma unroll
+    for (int z = 0; z < TZ; ++z) v[z] = row[z];
+#pragma unroll
+    for (int z = 0; z < TZ; ++z) tileF[lane * TZ + z] = v[z];
+  }
+  __syncthreads();
+  for (int base = 0; base < it.count; base += 64) {
+    const int e = base + lane;
+    const bool valid = e < it.count;
+    const int q = list[it.start + (valid ? e : 0)];
+    const NodeRec<T>* nd = nodes + q;
+    // weight of tile position i on an axis: support index (tile origin + i - support origin)
+    // mod n_fine, zero outside [0, w); i < tile extent <= n_fine, so one subtraction reduces
+    auto weight = [&](int d0, int i, int n, int w, int a) {
+      int d = d0 + i;
+      if (d >= n) d -= n;
+      const bool in = valid && d < w;
+      const T v = nd->w[a][in ? d : 0];
+      return in ? static_cast<double>(v) : 0.0;
+    };
+    const int dx = mod_fine(x0 - nd->l0[0], nf0);
+    const int dy = mod_fine(y0 - nd->l0[1], nf1);
+    const int dz = mod_fine(z0 - nd->l0[2], nf2);
+    double wx[TX], wy[TY], wz[TZ];
+#pragma unroll
+    for (int i = 0; i < TX; ++i) wx[i] = weight(dx, i, nf0, w0, 0);
+#pragma unroll
+    for (int i = 0; i < TY; ++i) wy[i] = weight(dy, i, nf1, w1, 1);
+#pragma unroll
+    for (int i = 0; i < TZ; ++i) wz[i] = weight(dz, i, nf2, w2, 2);
+    double ar = 0.0, ai = 0.0;
+    for (int x = 0; x < TX; ++x) {
+      const C<T>* plane = tileF + x * TY * TZ;
+      double tr = 0.0, ti = 0.0;
+#pragma unroll
+      for (int y = 0; y < TY; ++y) {
+        const C<T>* col = plane + y * TZ;
+        double sr = 0.0, si = 0.0;
+#pragma unroll
+        for (int z = 0; z < TZ; ++z) {
+          const C<T> f = col[z];
+          sr += wz[z] * static_cast<double>(f.re);
+          si += wz[z] * static_cast<double>(f.im);
+        }
+        tr += wy[y] * sr;
+        ti += wy[y] * si;
+      }
+      ar += wx[x] * tr;
+      ai += wx[x] * ti;
+    }
+    if (valid) part[static_cast<int64_t>(it.start) + e] = C<double>{ar, ai};
+  }
+}
+
+// Sum the partials of each node (its list positions, in list order) and apply the node scale.
+template <typename T>
+__global__ void __launch_bounds__(256) k_interp_gather(const C<double>* __restrict__ part,
+                                                       const int32_t* __restrict__ gptr,
+                                                       const int32_t* __restrict__ gpos, int64_t M,
+                                                       const double* __restrict__ scale, double sscalar,
+                                                       C<T>* __restrict__ out) {
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (q >= M) return;
+  const int b = gptr[q], e = gptr[q + 1];
+  if (b == e) return;                        // node outside the scheduled set
+  double sr = 0.0, si = 0.0;
+  for (int j = b; j < e; ++j) {
+    const C<double> v = part[gpos[j]];
+    sr += v.re;
+    si += v.im;
+  }
+  const double s = scale ? scale[q] * sscalar : sscalar;
+  out[q] = C<T>{static_cast<T>(s * sr), static_cast<T>(s * si)};
+}
+
 // Sum the partial tiles of each split tile in slot order (deterministic); one thread per point.
 template <typename T, int TX, int TY>
 __global__ void __launch_bounds__(64 * kTileZ) k_spread_reduce(C<T>* __restrict__ F,
@@ -413,25 +519,53 @@ static hipError_t interp_d(DevicePlan& P, int which, C<T>* out, const double* sc
 }
 
 template <typename T>
+static hipError_t interp_tile_t(DevicePlan& P, int which, C<T>* out, const double* scale, double sscalar,
+                                hipStream_t s) {
+  const HostTables& H = P.H;
+  const Schedule& S = H.sched[which];
+  const DevicePlan::DevSchedule& D = P.dsched[which];
+  const int nitems = static_cast<int>(S.items.size());
+  if (nitems > 0 && !S.list.empty()) {
+    hipLaunchKernelGGL((k_interp_col<T>), dim3(nitems), dim3(64), 0, s,
+                       reinterpret_cast<const C<T>*>(P.fine), reinterpret_cast<const NodeRec<T>*>(P.nodes), D.list,
+                       D.items, H.nf[0], H.nf[1], H.nf[2], H.ntiles[1], H.ntiles[2], H.W[0], H.W[1], H.W[2],
+                       reinterpret_cast<C<double>*>(P.ipartial));
+    DDI_CHECK(hipGetLastError());
+  }
+  if (H.M > 0) {
+    const int blocks = static_cast<int>((H.M + 255) / 256);
+    hipLaunchKernelGGL((k_interp_gather<T>), dim3(blocks), dim3(256), 0, s,
+                       reinterpret_cast<const C<double>*>(P.ipartial), D.gptr, D.gpos, H.M, scale, sscalar, out);
+    DDI_CHECK(hipGetLastError());
+  }
+  return hipSuccess;
+}
+
+template <typename T>
 static hipError_t interp(DevicePlan& P, int which, C<T>* out, const double* scale, double sscalar,
                          hipStream_t s) {
-  switch (P.H.w) {
-    case 2: return interp_d<T, 2>(P, which, out, scale, sscalar, s);
-    case 3: return interp_d<T, 3>(P, which, out, scale, sscalar, s);
-    case 4: return interp_d<T, 4>(P, which, out, scale, sscalar, s);
-    case 5: return interp_d<T, 5>(P, which, out, scale, sscalar, s);
-    case 6: return interp_d<T, 6>(P, which, out, scale, sscalar, s);
-    case 7: return interp_d<T, 7>(P, which, out, scale, sscalar, s);
-    case 8: return interp_d<T, 8>(P, which, out, scale, sscalar, s);
-    case 9: return interp_d<T, 9>(P, which, out, scale, sscalar, s);
-    case 10: return interp_d<T, 10>(P, which, out, scale, sscalar, s);
-    case 11: return interp_d<T, 11>(P, which, out, scale, sscalar, s);
-    case 12: return interp_d<T, 12>(P, which, out, scale, sscalar, s);
-    case 13: return interp_d<T, 13>(P, which, out, scale, sscalar, s);
-    case 14: return interp_d<T, 14>(P, which, out, scale, sscalar, s);
-    case 15: return interp_d<T, 15>(P, which, out, scale, sscalar, s);
-    case 16: return interp_d<T, 16>(P, which, out, scale, sscalar, s);
-    default: return hipErrorInvalidValue;
+  if constexpr (kInterpTile && sizeof(T) == 8) {
+    if (P.H.tile[0] == 8 && P.H.tile[1] == 8) return interp_tile_t<T>(P, which, out, scale, sscalar, s);
+  }
+  {
+    switch (P.H.w) {
+      case 2: return interp_d<T, 2>(P, which, out, scale, sscalar, s);
+      case 3: return interp_d<T, 3>(P, which, out, scale, sscalar, s);
+      case 4: return interp_d<T, 4>(P, which, out, scale, sscalar, s);
+      case 5: return interp_d<T, 5>(P, which, out, scale, sscalar, s);
+      case 6: return interp_d<T, 6>(P, which, out, scale, sscalar, s);
+      case 7: return interp_d<T, 7>(P, which, out, scale, sscalar, s);
+      case 8: return interp_d<T, 8>(P, which, out, scale, sscalar, s);
+      case 9: return interp_d<T, 9>(P, which, out, scale, sscalar, s);
+      case 10: return interp_d<T, 10>(P, which, out, scale, sscalar, s);
+      case 11: return interp_d<T, 11>(P, which, out, scale, sscalar, s);
+      case 12: return interp_d<T, 12>(P, which, out, scale, sscalar, s);
+      case 13: return interp_d<T, 13>(P, which, out, scale, sscalar, s);
+      case 14: return interp_d<T, 14>(P, which, out, scale, sscalar, s);
+      case 15: return interp_d<T, 15>(P, which, out, scale, sscalar, s);
+      case 16: return interp_d<T, 16>(P, which, out, scale, sscalar, s);
+      default: return hipErrorInvalidValue;
+    }
   }
 }
 

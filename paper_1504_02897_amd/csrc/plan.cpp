@@ -222,6 +222,15 @@ std::string build_spread_schedule(const HostTables& t, const std::vector<int64_t
                    [](const SpreadItem& x, const SpreadItem& y) { return x.count > y.count; });
 #endif
   S.nslots = slot;
+  // per node, the positions of its entries in the list (in list order)
+  S.gptr.assign(M + 1, 0);
+  for (int32_t q : S.list) S.gptr[q + 1]++;
+  for (int64_t q = 0; q < M; ++q) S.gptr[q + 1] += S.gptr[q];
+  S.gpos.assign(S.list.size(), 0);
+  {
+    std::vector<int32_t> fillg(S.gptr.begin(), S.gptr.end() - 1);
+    for (size_t i = 0; i < S.list.size(); ++i) S.gpos[fillg[S.list[i]]++] = static_cast<int32_t>(i);
+  }
   return "";
 }
 
