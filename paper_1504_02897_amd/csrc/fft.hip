@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "fft.h"
 
@@ -84,68 +85,106 @@ template <> struct RadixPlan<128> { static constexpr int R1 = 16, R2 = 8, R3 = 1
 template <> struct RadixPlan<256> { static constexpr int R1 = 16, R2 = 16, R3 = 1; };
 template <> struct RadixPlan<512> { static constexpr int R1 = 8, R2 = 8, R3 = 8; };
 template <> struct RadixPlan<1024> { static constexpr int R1 = 16, R2 = 16, R3 = 4; };
+// Plan per element type and pass kind: FP64 256-point lines along the contiguous axis use
+// radix 8 x 8 x 4 (eight values per thread: half the registers of radix 16, one more LDS
+// exchange); measured slower for the strided passes, which keep radix 16 x 16.
+template <typename T, int N, bool CONTIG> struct Radix : RadixPlan<N> {};
+template <> struct Radix<double, 256, true> { static constexpr int R1 = 8, R2 = 8, R3 = 4; };
 
-// One Stockham pass (radix R, Ns = product of earlier radices) over LDS, for the
-// butterflies j = j0 + TL*b owned by this thread.  The thread's registers hold
-// R1 values (R1/R butterflies of R values).
-template <typename T, int N, int R1, int R, int SIGN, typename Addr>
-__device__ __forceinline__ void stockham_load(C<T>* lds, Addr addr, int j0, int Ns, const C<T>* __restrict__ tw,
-                                              C<T>* v) {
+// FP64 lines of up to 512 points exchange the real parts through LDS, then the imaginary
+// parts: half the LDS footprint of a line (twice the resident lines per CU) for the same
+// bytes moved.
+template <typename T, int N>
+struct SplitExchange {
+  static constexpr bool value = sizeof(T) == 8 && N <= 512;   // measured slower for 1024-point lines
+};
+template <typename T, int N>
+using LdsElem = typename std::conditional<SplitExchange<T, N>::value, T, C<T>>::type;
+
+// One LDS exchange between radix passes: the thread's R1 values (grouped for radix Rs,
+// written with stride Ns) are stored, then regathered for radix Rl.  On exit v holds the
+// raw (untwiddled) inputs of the next pass.
+template <typename T, int N, int R1, int Rs, int Rl, typename Addr>
+__device__ __forceinline__ void stockham_exchange(LdsElem<T, N>* lds, Addr addr, int j0, int Ns, C<T>* v) {
   constexpr int TL = N / R1;
-  constexpr int NB = R1 / R;
+  if constexpr (SplitExchange<T, N>::value) {
+    T keep[R1];
 #pragma unroll
-  for (int b = 0; b < NB; ++b) {
-    const int j = j0 + TL * b;
-    const int jm = j % Ns;
+    for (int part = 0; part < 2; ++part) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      C<T> x = lds[addr(j + r * (N / R))];
-      if (r > 0) {
-        C<T> w = tw[(r * jm * (N / (Ns * R))) & (N - 1)];
-        if (SIGN > 0) w.im = -w.im;
-        x = cmul(x, w);
+      for (int b = 0; b < R1 / Rs; ++b) {
+        const int j = j0 + TL * b;
+        const int idxD = (j / Ns) * Ns * Rs + (j % Ns);
+#pragma unroll
+        for (int r = 0; r < Rs; ++r) lds[addr(idxD + r * Ns)] = part == 0 ? v[b * Rs + r].re : v[b * Rs + r].im;
       }
-      v[b * R + r] = x;
+      __syncthreads();
+#pragma unroll
+      for (int b = 0; b < R1 / Rl; ++b) {
+        const int j = j0 + TL * b;
+#pragma unroll
+        for (int r = 0; r < Rl; ++r) {
+          const T x = lds[addr(j + r * (N / Rl))];
+          if (part == 0) keep[b * Rl + r] = x;
+          else v[b * Rl + r] = C<T>{keep[b * Rl + r], x};
+        }
+      }
+      if (part == 0) __syncthreads();
+    }
+  } else {
+#pragma unroll
+    for (int b = 0; b < R1 / Rs; ++b) {
+      const int j = j0 + TL * b;
+      const int idxD = (j / Ns) * Ns * Rs + (j % Ns);
+#pragma unroll
+      for (int r = 0; r < Rs; ++r) lds[addr(idxD + r * Ns)] = v[b * Rs + r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < R1 / Rl; ++b) {
+      const int j = j0 + TL * b;
+#pragma unroll
+      for (int r = 0; r < Rl; ++r) v[b * Rl + r] = lds[addr(j + r * (N / Rl))];
+    }
+  }
+}
+
+// Twiddles and radix-R DFTs of one Stockham pass (Ns = product of the earlier radices) on
+// the thread's R1 values.
+template <typename T, int N, int R1, int R, int SIGN>
+__device__ __forceinline__ void stockham_compute(int j0, int Ns, const C<T>* __restrict__ tw, C<T>* v) {
+  constexpr int TL = N / R1;
+#pragma unroll
+  for (int b = 0; b < R1 / R; ++b) {
+    const int jm = (j0 + TL * b) % Ns;
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      C<T> w = tw[(r * jm * (N / (Ns * R))) & (N - 1)];
+      if (SIGN > 0) w.im = -w.im;
+      v[b * R + r] = cmul(v[b * R + r], w);
     }
     dft_regs<T, R, SIGN>(v + b * R);
   }
 }
 
-template <typename T, int N, int R1, int R, typename Addr>
-__device__ __forceinline__ void stockham_store(C<T>* lds, Addr addr, int j0, int Ns, const C<T>* v) {
-  constexpr int TL = N / R1;
-  constexpr int NB = R1 / R;
-#pragma unroll
-  for (int b = 0; b < NB; ++b) {
-    const int j = j0 + TL * b;
-    const int idxD = (j / Ns) * Ns * R + (j % Ns);
-#pragma unroll
-    for (int r = 0; r < R; ++r) lds[addr(idxD + r * Ns)] = v[b * R + r];
-  }
-}
-
 // Full line FFT.  On entry v[r] = x[j0 + r*TL] (r < R1).  On exit the thread
 // holds the outputs k = j + r*(N/Rlast), j = j0 + TL*b, in v[b*Rlast + r].
-template <typename T, int N, int SIGN, typename Addr>
-__device__ __forceinline__ void line_fft(C<T>* lds, Addr addr, int j0, const C<T>* __restrict__ tw, C<T>* v) {
-  using P = RadixPlan<N>;
+template <typename T, int N, int SIGN, typename P, typename Addr>
+__device__ __forceinline__ void line_fft(LdsElem<T, N>* lds, Addr addr, int j0, const C<T>* __restrict__ tw, C<T>* v) {
   dft_regs<T, P::R1, SIGN>(v);
   if constexpr (P::R2 > 1) {
-    stockham_store<T, N, P::R1, P::R1>(lds, addr, j0, 1, v);
-    __syncthreads();
-    stockham_load<T, N, P::R1, P::R2, SIGN>(lds, addr, j0, P::R1, tw, v);
+    stockham_exchange<T, N, P::R1, P::R1, P::R2>(lds, addr, j0, 1, v);
+    stockham_compute<T, N, P::R1, P::R2, SIGN>(j0, P::R1, tw, v);
     if constexpr (P::R3 > 1) {
       __syncthreads();
-      stockham_store<T, N, P::R1, P::R2>(lds, addr, j0, P::R1, v);
-      __syncthreads();
-      stockham_load<T, N, P::R1, P::R3, SIGN>(lds, addr, j0, P::R1 * P::R2, tw, v);
+      stockham_exchange<T, N, P::R1, P::R2, P::R3>(lds, addr, j0, P::R1, v);
+      stockham_compute<T, N, P::R1, P::R3, SIGN>(j0, P::R1 * P::R2, tw, v);
     }
   }
 }
 
-template <int N>
+template <typename P, int N>
 struct LineOut {
-  using P = RadixPlan<N>;
   static constexpr int RL = P::R3 > 1 ? P::R3 : (P::R2 > 1 ? P::R2 : P::R1);
   static constexpr int TL = N / P::R1;
   // output index held in v[i] by thread j0
@@ -174,8 +213,8 @@ __global__ void __launch_bounds__(MAXT) k_fft_strided(C<T>* __restrict__ F, int 
                                                      int n_o, int o_compact, int nc_axis, int in_compact,
                                                      int out_compact, const C<T>* __restrict__ tw, int B) {
   extern __shared__ unsigned char smem_raw[];
-  C<T>* lds = reinterpret_cast<C<T>*>(smem_raw);
-  using P = RadixPlan<N>;
+  LdsElem<T, N>* lds = reinterpret_cast<LdsElem<T, N>*>(smem_raw);
+  using P = Radix<T, N, false>;
   constexpr int TL = N / P::R1;
   const int b = threadIdx.x % B;
   const int j0 = threadIdx.x / B;
@@ -196,10 +235,10 @@ __global__ void __launch_bounds__(MAXT) k_fft_strided(C<T>* __restrict__ F, int 
     if (in_compact && !active(k, N, nc_axis)) v[r] = C<T>{0, 0};
     else v[r] = F[base + k * stride];
   }
-  line_fft<T, N, SIGN>(lds, addr, j0, tw, v);
+  line_fft<T, N, SIGN, P>(lds, addr, j0, tw, v);
 #pragma unroll
   for (int i = 0; i < P::R1; ++i) {
-    const int k = LineOut<N>::k(j0, i);
+    const int k = LineOut<P, N>::k(j0, i);
     if (!out_compact || active(k, N, nc_axis)) F[base + k * stride] = v[i];
   }
 }
@@ -220,8 +259,8 @@ __global__ void __launch_bounds__(256) k_fft_contig(const void* in, void* out,
                                                     const double* __restrict__ D2,
                                                     const C<T>* __restrict__ tw, int B, int nlines) {
   extern __shared__ unsigned char smem_raw[];
-  C<T>* lds = reinterpret_cast<C<T>*>(smem_raw);
-  using P = RadixPlan<N>;
+  LdsElem<T, N>* lds = reinterpret_cast<LdsElem<T, N>*>(smem_raw);
+  using P = Radix<T, N, true>;
   constexpr int TL = N / P::R1;
   constexpr int LS = N + N / P::R1;      // padded line stride in LDS
   const int j0 = threadIdx.x % TL;
@@ -230,8 +269,8 @@ __global__ void __launch_bounds__(256) k_fft_contig(const void* in, void* out,
   const bool valid = line < nlines;
   const int o0 = valid ? line / n1 : 0;
   const int o1 = valid ? line % n1 : 0;
-  C<T>* my = lds + lb * LS;
-  auto addr = [](int k) { return k + k / RadixPlan<N>::R1; };
+  LdsElem<T, N>* my = lds + lb * LS;
+  auto addr = [](int k) { return k + k / Radix<T, N, true>::R1; };
   C<T> v[P::R1];
   if (MODE == R2C_PAD) {
     const T* rho = reinterpret_cast<const T*>(in);
@@ -258,7 +297,7 @@ __global__ void __launch_bounds__(256) k_fft_contig(const void* in, void* out,
       v[r] = valid ? F[lbase + k] : C<T>{0, 0};
     }
   }
-  line_fft<T, N, SIGN>(my, addr, j0, tw, v);
+  line_fft<T, N, SIGN, P>(my, addr, j0, tw, v);
   if (!valid) return;
   if (MODE == C2R_TRUNC) {
     T* phi = reinterpret_cast<T*>(out);
@@ -266,7 +305,7 @@ __global__ void __launch_bounds__(256) k_fft_contig(const void* in, void* out,
     const int64_t rb = (static_cast<int64_t>(o0) * n1 + o1) * nc2;
 #pragma unroll
     for (int i = 0; i < P::R1; ++i) {
-      const int k = LineOut<N>::k(j0, i);
+      const int k = LineOut<P, N>::k(j0, i);
       if (active(k, N, nc2)) {
         const int c2 = cmap(k, N, nc2);
         phi[rb + c2] = static_cast<T>(static_cast<double>(v[i].re) * s01 * D2[c2]);
@@ -278,7 +317,7 @@ __global__ void __launch_bounds__(256) k_fft_contig(const void* in, void* out,
     if (MODE == C2C) lbase = static_cast<int64_t>(line) * N;
     else lbase = (static_cast<int64_t>(fmap(o0, d0, n0)) * d1 + fmap(o1, d1, n1)) * N;
 #pragma unroll
-    for (int i = 0; i < P::R1; ++i) F[lbase + LineOut<N>::k(j0, i)] = v[i];
+    for (int i = 0; i < P::R1; ++i) F[lbase + LineOut<P, N>::k(j0, i)] = v[i];
   }
 }
 
@@ -286,15 +325,15 @@ __global__ void __launch_bounds__(256) k_fft_contig(const void* in, void* out,
 template <typename T, int N, int SIGN>
 static hipError_t launch_strided_n(C<T>* F, int axis, int d0, int d1, int d2, int n_o, int o_compact, int nc,
                                    int in_c, int out_c, const C<T>* tw, hipStream_t s) {
-  constexpr int TL = N / RadixPlan<N>::R1;
+  constexpr int TL = N / Radix<T, N, false>::R1;
   // lines per workgroup: at least 256 threads, and row segments of >= 128 B along the
   // contiguous axis (coalescing) as far as 1024 threads and 64 KB of LDS allow
   int B = 256 / TL;
   while (B * static_cast<int>(sizeof(C<T>)) < 128 && 2 * B * TL <= 1024 &&
-         static_cast<size_t>(2 * B) * N * sizeof(C<T>) <= 65536)
+         static_cast<size_t>(2 * B) * N * sizeof(LdsElem<T, N>) <= 65536)
     B *= 2;
   while (B > d2) B >>= 1;
-  const size_t shm = static_cast<size_t>(B) * N * sizeof(C<T>);
+  const size_t shm = static_cast<size_t>(B) * N * sizeof(LdsElem<T, N>);
   const int blocks = n_o * (d2 / B);
   if (B * TL <= 256)
     hipLaunchKernelGGL((k_fft_strided<T, N, SIGN, 256>), dim3(blocks), dim3(B * TL), shm, s, F, axis, d0, d1, d2,
@@ -325,12 +364,12 @@ template <typename T, int N, int SIGN, int MODE>
 static hipError_t launch_contig_n(const void* in, void* out, int n0, int n1, int d0, int d1, int nc2,
                                   const double* D0, const double* D1, const double* D2, const C<T>* tw,
                                   hipStream_t s) {
-  constexpr int TL = N / RadixPlan<N>::R1;
-  constexpr int LS = N + N / RadixPlan<N>::R1;
+  constexpr int TL = N / Radix<T, N, true>::R1;
+  constexpr int LS = N + N / Radix<T, N, true>::R1;
   int B = 256 / TL;
-  while (B > 1 && static_cast<size_t>(B) * LS * sizeof(C<T>) > 65536) B >>= 1;
+  while (B > 1 && static_cast<size_t>(B) * LS * sizeof(LdsElem<T, N>) > 65536) B >>= 1;
   const int nlines = n0 * n1;
-  const size_t shm = static_cast<size_t>(B) * LS * sizeof(C<T>);
+  const size_t shm = static_cast<size_t>(B) * LS * sizeof(LdsElem<T, N>);
   const int blocks = (nlines + B - 1) / B;
   hipLaunchKernelGGL((k_fft_contig<T, N, SIGN, MODE>), dim3(blocks), dim3(B * TL), shm, s, in, out, n0, n1, d0, d1,
                      nc2, D0, D1, D2, tw, B, nlines);
