@@ -382,11 +382,22 @@ __global__ void __launch_bounds__(256) k_interp_gather(const C<double>* __restri
   if (q >= M) return;
   const int b = gptr[q], e = gptr[q + 1];
   if (b == e) return;                        // node outside the scheduled set
+  // eight entries per round, all loads in flight, summed in list order
   double sr = 0.0, si = 0.0;
-  for (int j = b; j < e; ++j) {
-    const C<double> v = part[gpos[j]];
-    sr += v.re;
-    si += v.im;
+  for (int j0 = b; j0 < e; j0 += 8) {
+    int pos[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) pos[j] = gpos[j0 + j < e ? j0 + j : b];
+    C<double> v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = part[pos[j]];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (j0 + j < e) {
+        sr += v[j].re;
+        si += v[j].im;
+      }
+    }
   }
   const double s = scale ? scale[q] * sscalar : sscalar;
   out[q] = C<T>{static_cast<T>(s * sr), static_cast<T>(s * si)};
