@@ -45,9 +45,9 @@ hipError_t upload(X** dst, const X* src, size_t count, hipStream_t s, int64_t& b
 
 void free_plan(ddi::DevicePlan& P) {
   void* ptrs[] = {P.nodes, P.c_scaled, P.c_half, P.deconv[0], P.deconv[1], P.deconv[2],
-                  P.fine, P.gnodes, P.partial, P.ipartial, P.gpe_rho, P.gpe_phi, P.gpe_phit, P.gpe_c1, P.gpe_c2, P.gpe_red};
+                  P.fine, P.gnodes, P.partial, P.ipartial, P.pads, P.gpe_rho, P.gpe_phi, P.gpe_phit, P.gpe_c1, P.gpe_c2, P.gpe_red};
   for (auto& d : P.dsched) {
-    void* sp[] = {d.list, d.items, d.reduces, d.interp_items, d.interp_direct, d.gptr, d.gpos};
+    void* sp[] = {d.list, d.items, d.reduces, d.interp_items, d.interp_direct, d.gptr, d.gpos, d.ent};
     for (void* p : sp)
       if (p) (void)hipFree(p);
   }
@@ -59,7 +59,7 @@ void free_plan(ddi::DevicePlan& P) {
 
 template <typename T>
 ddi_status build_device(ddi::DevicePlan& P, hipStream_t s, std::vector<ddi::NodeRec<T>>& recs,
-                        std::vector<std::vector<ddi::Complex<T>>>& tws) {
+                        std::vector<std::vector<ddi::Complex<T>>>& tws, std::vector<T>& padrows) {
   const ddi::HostTables& H = P.H;
   int64_t& bytes = P.workspace_bytes;
   recs.resize(H.M);
@@ -93,7 +93,18 @@ ddi_status build_device(ddi::DevicePlan& P, hipStream_t s, std::vector<ddi::Node
     if (ddi::kInterpTile && sizeof(T) == 8 && H.tile[0] == 8) {
       HIP_TRY(upload(&D.gptr, S.gptr.data(), S.gptr.size(), s, bytes), "upload interp gather");
       HIP_TRY(upload(&D.gpos, S.gpos.data(), S.gpos.size(), s, bytes), "upload interp gather");
+      if (H.padded_rows) HIP_TRY(upload(&D.ent, S.ent.data(), S.ent.size(), s, bytes), "upload entry table");
     }
+  }
+  if (ddi::kInterpTile && sizeof(T) == 8 && H.padded_rows) {
+    padrows.assign(static_cast<size_t>(H.M) * 3 * ddi::kPadRow, T(0));
+    for (int64_t q = 0; q < H.M; ++q)
+      for (int a = 0; a < 3; ++a)
+        for (int i = 0; i < ddi::kWMax; ++i)
+          padrows[(q * 3 + a) * ddi::kPadRow + ddi::kPadOff + i] = static_cast<T>(H.wts[(q * 3 + a) * ddi::kWMax + i]);
+    T* dp = nullptr;
+    HIP_TRY(upload(&dp, padrows.data(), padrows.size(), s, bytes), "upload padded weight rows");
+    P.pads = dp;
   }
   // twiddles for every FFT length used: fine grid sizes and the unpadded sizes
   tws.assign(11, {});
@@ -209,8 +220,10 @@ ddi_status ddi_plan(const ddi_params* params, void* stream, ddi_plan_t* out) {
   std::vector<ddi::NodeRec<float>> rf;
   std::vector<std::vector<ddi::Complex<double>>> td;
   std::vector<std::vector<ddi::Complex<float>>> tf;
+  std::vector<double> pd;
+  std::vector<float> pf;
   try {
-    ds = P.mixed ? build_device<float>(P, s, rf, tf) : build_device<double>(P, s, rd, td);
+    ds = P.mixed ? build_device<float>(P, s, rf, tf, pf) : build_device<double>(P, s, rd, td, pd);
   } catch (const std::bad_alloc&) {
     ds = fail(DDI_ENOMEM, "host allocation failed while uploading plan tables");
   }

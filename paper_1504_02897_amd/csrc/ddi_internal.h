@@ -33,6 +33,8 @@ constexpr int kSpreadBatch = DDI_SPREAD_BATCH;
 #ifndef DDI_SPREAD_UNROLL
 #define DDI_SPREAD_UNROLL 4
 #endif
+constexpr int kPadRow = 32;       // zero-padded weight row: 8 zeros, the w weights, zeros
+constexpr int kPadOff = 8;
 #ifndef DDI_INTERP_TILE
 #define DDI_INTERP_TILE 1
 #endif
@@ -40,6 +42,11 @@ constexpr int kSpreadBatch = DDI_SPREAD_BATCH;
 // lanes are (tile, node) entries; one partial per entry, gathered per node); 0 = node-owned
 // (LDS-staged groups plus direct reads of the fine grid), which FP32 and 2D always use
 constexpr bool kInterpTile = DDI_INTERP_TILE != 0;
+#ifndef DDI_INTERP_MFMA
+#define DDI_INTERP_MFMA 1
+#endif
+// tile-owned FP64 interpolation on the matrix cores where the plan has padded weight rows
+constexpr bool kInterpMfma = DDI_INTERP_MFMA != 0;
 
 // One quadrature node as seen by the spread / interpolation kernels: the first
 // fine-grid index of its support on each axis (already reduced mod n_fine) and
@@ -89,6 +96,10 @@ struct Schedule {
   // are gpos[gptr[q] .. gptr[q+1]) (increasing)
   std::vector<int32_t> gptr;
   std::vector<int32_t> gpos;
+  // padded-row form (see HostTables::padded_rows): per list entry i, ent[2i] = node and
+  // ent[2i+1] = kPadOff + s_a packed as bytes x | y << 8 | z << 16, where s_a in [-7, w-1]
+  // is the tile origin minus the support origin on axis a
+  std::vector<int32_t> ent;
 };
 
 // The two node subsets a plan schedules.  kAll: every node (the type-2 / type-1 entry
@@ -124,6 +135,9 @@ struct HostTables {
   // per node: 2 for the kept member of a complete +-k pair, 1 for a node whose partner
   // was masked out, 0 for the partner that is not kept in the half set
   std::vector<double> half_factor;
+  // 3D with 8 x 8 x 8 tiles and n_fine >= w + 8 on every axis: a node's weights at a tile's
+  // positions are one contiguous run of a zero-padded row (no periodic wrap inside a tile)
+  bool padded_rows = false;
   Schedule sched[2];
 };
 
@@ -172,6 +186,7 @@ struct DevicePlan {
     int32_t* interp_direct = nullptr;
     int32_t* gptr = nullptr;
     int32_t* gpos = nullptr;
+    int32_t* ent = nullptr;
   } dsched[2];
   bool interp_lds_ready = false;
   void* twiddles[11] = {};       // per log2(n): Complex<T>[n]
@@ -180,6 +195,7 @@ struct DevicePlan {
   void* gnodes = nullptr;        // Complex<T>[M]
   void* partial = nullptr;       // Complex<T>[nslots][tile volume]
   void* ipartial = nullptr;      // Complex<double>[spread entries]: interpolation partial sums
+  void* pads = nullptr;          // T[M][3][kPadRow]: zero-padded weight rows
   int64_t workspace_bytes = 0;
   // GPE workspace (allocated on first use)
   void* gpe_rho = nullptr;       // T[N]

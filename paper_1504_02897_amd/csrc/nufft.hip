@@ -371,6 +371,132 @@ __global__ void __launch_bounds__(64) k_interp_col(const C<T>* __restrict__ F, c
   }
 }
 
+// Matrix-core form of the same tile interpolation (FP64, 3D, padded weight rows).  For the
+// entries of a tile the partials are a dense product followed by a short weighting:
+//   G[e][(x,p)] = sum_{(y,z)} A[e][(y,z)] B[(y,z)][(x,p)],  A[e][(y,z)] = wy_e[y] wz_e[z],
+//   B[(y,z)][(x,p)] = part p (re, im) of F[x][y][z],           partial_e,p = sum_x wx_e[x] G[e][(x,p)].
+// v_mfma_f64_16x16x4f64 takes A[i][k] from lane i + 16k, B[k][j] from lane j + 16k and
+// leaves D[i][j] in lane j + 16 (i % 4), item i / 4.  Rows are entries (16 per block), the
+// 16 columns are (x, p), and K = (y, z) runs over 16 steps of 4: at step s lane group k
+// covers y = 4 (k / 2) + s / 4, z = 4 (k % 2) + s % 4, so a lane needs four y and four z
+// weights of its entry.  B is staged in LDS once per item in fragment order (each lane reads
+// its own element); the weights of a row block are loaded cooperatively (eight lanes per
+// contiguous run of a padded row) and published through LDS, their loads pipelined across
+// the blocks' matrix products.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+__global__ void __launch_bounds__(64) k_interp_mfma(const C<T>* __restrict__ F, const T* __restrict__ pads,
+                                                    const int2* __restrict__ ent,
+                                                    const SpreadItem* __restrict__ items, int nf1, int nf2, int nt1,
+                                                    int nt2, C<double>* __restrict__ part) {
+  const int lane = threadIdx.x;
+  const SpreadItem it = items[blockIdx.x];
+  if (it.tile < 0 || it.count == 0) return;  // padding item or empty tile
+  const int tz = it.tile % nt2;
+  const int ty = (it.tile / nt2) % nt1;
+  const int tx = it.tile / (nt2 * nt1);
+  constexpr int SB = 65;                     // fragment step stride (one pad: conflict-free staging)
+  __shared__ double fragB[16 * SB];
+  __shared__ double wts[16 * 24];            // [entry of the block][axis][8 tile positions]
+  const int nmb = (it.count + 15) / 16;
+  // Weights of a row block are loaded cooperatively: load j covers windows 8 j .. 8 j + 7
+  // (window w = entry w / 3, axis w % 3), eight lanes per contiguous run of a padded row.
+  // The two dependent loads are pipelined across blocks: entry records two blocks ahead,
+  // padded rows one block ahead.
+  auto load_ent = [&](int mb, int2* en) {
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const int e = 16 * mb + (8 * j + (lane >> 3)) / 3;
+      en[j] = ent[it.start + (e < it.count ? e : 0)];
+    }
+  };
+  auto load_rows = [&](int mb, const int2* en, double* raw) {
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const int w = 8 * j + (lane >> 3);
+      const int e = 16 * mb + w / 3, a = w % 3;
+      const int b = (en[j].y >> (8 * a)) & 255;
+      const T v = pads[static_cast<int64_t>(en[j].x) * (3 * kPadRow) + a * kPadRow + b + (lane & 7)];
+      raw[j] = e < it.count ? static_cast<double>(v) : 0.0;
+    }
+  };
+  int2 en_a[6], en_b[6];
+  double raw[6];
+  load_ent(0, en_a);
+  if (nmb > 1) load_ent(1, en_b);
+  {
+    // the tile, eight lanes per 128-byte row: load r covers columns 8 r .. 8 r + 7
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int c = 8 * r + (lane >> 3), cx = c >> 3, cy = c & 7, z = lane & 7;
+      const C<T> v = F[(static_cast<int64_t>(tx * 8 + cx) * nf1 + (ty * 8 + cy)) * nf2 + tz * kTileZ + z];
+      const int at = (4 * (cy & 3) + (z & 3)) * SB + (2 * (cy >> 2) + (z >> 2)) * 16 + 2 * cx;
+      fragB[at] = static_cast<double>(v.re);
+      fragB[at + 1] = static_cast<double>(v.im);
+    }
+  }
+  load_rows(0, en_a, raw);
+#pragma unroll
+  for (int j = 0; j < 6; ++j) wts[64 * j + lane] = raw[j];
+  __syncthreads();
+  const int kk = lane >> 4, col = lane & 15, xo = col >> 1;
+  const int yo = 4 * (kk >> 1), zo = 4 * (kk & 1);
+  const bool b3 = (lane & 8) != 0, b2 = (lane & 4) != 0;
+  for (int mb = 0; mb < nmb; ++mb) {
+    double wy[4], wz[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      wy[i] = wts[col * 24 + 8 + yo + i];
+      wz[i] = wts[col * 24 + 16 + zo + i];
+    }
+    const double wxa = wts[col * 24 + 2 * kk], wxb = wts[col * 24 + 2 * kk + 1];
+    // en_b holds block mb + 1's entry records: start its rows, and block mb + 2's records
+    const bool more = mb + 1 < nmb;
+    if (more) {
+      load_rows(mb + 1, en_b, raw);
+#pragma unroll
+      for (int j = 0; j < 6; ++j) en_a[j] = en_b[j];
+      if (mb + 2 < nmb) load_ent(mb + 2, en_b);
+    }
+    dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int st = 0; st < 16; ++st)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(wy[st >> 2] * wz[st & 3], fragB[st * SB + lane], acc, 0, 0, 0);
+    // item i holds row 4 i + kk (entry 16 mb + 4 i + kk), an A row of lane (4 i + kk) + 16 (xo / 2)
+    double v[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int src = (4 * i + kk) + 16 * (xo >> 1);
+      const double xa = __shfl(wxa, src, 64), xb = __shfl(wxb, src, 64);
+      v[i] = acc[i] * ((xo & 1) ? xb : xa);
+    }
+    // sum over x (lane bits 1..3) for the four items at once: exchange halves across bit 3,
+    // then bit 2, then add across bit 1; the lane ends with item b2 + 2 b3
+    double u[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const double send = b3 ? v[j] : v[j + 2], keep = b3 ? v[j + 2] : v[j];
+      u[j] = keep + __shfl_xor(send, 8, 64);
+    }
+    double r;
+    {
+      const double send = b2 ? u[0] : u[1], keep = b2 ? u[1] : u[0];
+      r = keep + __shfl_xor(send, 4, 64);
+    }
+    r += __shfl_xor(r, 2, 64);
+    const int er = 16 * mb + 4 * ((b2 ? 1 : 0) + (b3 ? 2 : 0)) + kk;
+    if ((lane & 2) == 0 && er < it.count)
+      reinterpret_cast<double*>(part + static_cast<int64_t>(it.start) + er)[lane & 1] = r;
+    if (more) {
+      __syncthreads();                       // every lane has read this block's weights
+#pragma unroll
+      for (int j = 0; j < 6; ++j) wts[64 * j + lane] = raw[j];
+      __syncthreads();
+    }
+  }
+}
+
 // Sum the partials of each node (its list positions, in list order) and apply the node scale.
 template <typename T>
 __global__ void __launch_bounds__(256) k_interp_gather(const C<double>* __restrict__ part,
@@ -537,10 +663,14 @@ static hipError_t interp_tile_t(DevicePlan& P, int which, C<T>* out, const doubl
   const DevicePlan::DevSchedule& D = P.dsched[which];
   const int nitems = static_cast<int>(S.items.size());
   if (nitems > 0 && !S.list.empty()) {
-    hipLaunchKernelGGL((k_interp_col<T>), dim3(nitems), dim3(64), 0, s,
-                       reinterpret_cast<const C<T>*>(P.fine), reinterpret_cast<const NodeRec<T>*>(P.nodes), D.list,
-                       D.items, H.nf[0], H.nf[1], H.nf[2], H.ntiles[1], H.ntiles[2], H.W[0], H.W[1], H.W[2],
-                       reinterpret_cast<C<double>*>(P.ipartial));
+    if (kInterpMfma && H.padded_rows)
+      hipLaunchKernelGGL((k_interp_mfma<T>), dim3(nitems), dim3(64), 0, s, reinterpret_cast<const C<T>*>(P.fine),
+                         reinterpret_cast<const T*>(P.pads), reinterpret_cast<const int2*>(D.ent), D.items, H.nf[1],
+                         H.nf[2], H.ntiles[1], H.ntiles[2], reinterpret_cast<C<double>*>(P.ipartial));
+    else
+      hipLaunchKernelGGL((k_interp_col<T>), dim3(nitems), dim3(64), 0, s, reinterpret_cast<const C<T>*>(P.fine),
+                         reinterpret_cast<const NodeRec<T>*>(P.nodes), D.list, D.items, H.nf[0], H.nf[1], H.nf[2],
+                         H.ntiles[1], H.ntiles[2], H.W[0], H.W[1], H.W[2], reinterpret_cast<C<double>*>(P.ipartial));
     DDI_CHECK(hipGetLastError());
   }
   if (H.M > 0) {
