@@ -47,6 +47,11 @@ constexpr bool kInterpTile = DDI_INTERP_TILE != 0;
 #endif
 // tile-owned FP64 interpolation on the matrix cores where the plan has padded weight rows
 constexpr bool kInterpMfma = DDI_INTERP_MFMA != 0;
+#ifndef DDI_SPREAD_MFMA
+#define DDI_SPREAD_MFMA 1
+#endif
+// FP64 spread on the matrix cores where the plan has padded weight rows
+constexpr bool kSpreadMfma = DDI_SPREAD_MFMA != 0;
 
 // One quadrature node as seen by the spread / interpolation kernels: the first
 // fine-grid index of its support on each axis (already reduced mod n_fine) and

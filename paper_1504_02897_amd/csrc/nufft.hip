@@ -290,6 +290,107 @@ __global__ void __launch_bounds__(64) k_spread(C<T>* __restrict__ F, C<T>* __res
   }
 }
 
+// Matrix-core form of the spread (FP64, 3D, padded weight rows): for a tile
+//   D[(y,z)][(x,p)] = sum_e A[e][(y,z)] Bs[e][(x,p)],  A[e][(y,z)] = wy_e[y] wz_e[z],
+//   Bs[e][(x,p)] = wx_e[x] (part p of g_e),
+// with K = entries (four per v_mfma_f64_16x16x4f64 step), four 16-row blocks of (y,z) rows
+// and N = (x, p): the whole tile accumulates in registers.  The weights and node values of
+// each stage of 16 entries are loaded cooperatively (eight lanes per contiguous run of a
+// padded row) and published through LDS, the next stage's loads in flight during the
+// current stage's products.  The tile goes through LDS and is written eight lanes per row
+// along the last axis (or to its partial slot, in k_spread's slot layout).
+template <typename T>
+__global__ void __launch_bounds__(64) k_spread_mfma(C<T>* __restrict__ F, C<T>* __restrict__ partial,
+                                                    const T* __restrict__ pads, const C<T>* __restrict__ g,
+                                                    const int2* __restrict__ ent,
+                                                    const SpreadItem* __restrict__ items, int nf1, int nf2, int nt1,
+                                                    int nt2) {
+  typedef double dbl4s __attribute__((ext_vector_type(4)));
+  const int lane = threadIdx.x;
+  const SpreadItem it = items[blockIdx.x];
+  if (it.tile < 0) return;                   // padding item
+  const int tz = it.tile % nt2;
+  const int ty = (it.tile / nt2) % nt1;
+  const int tx = it.tile / (nt2 * nt1);
+  __shared__ double wts[16 * 24];            // [entry of the stage][axis][8 tile positions]
+  __shared__ double gv[16 * 2];              // [entry of the stage][part]
+  constexpr int XS = 136;                    // x stride of the output staging (bank spread)
+  __shared__ double tileO[8 * XS];           // [x][y][z][part]
+  const int nst = (it.count + 15) / 16;
+  auto load_stage = [&](int st, double* raw, double& graw) {
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const int w = 8 * j + (lane >> 3);
+      const int e = 16 * st + w / 3, a = w % 3;
+      const bool valid = e < it.count;
+      const int2 en = ent[it.start + (valid ? e : 0)];
+      const int b = (en.y >> (8 * a)) & 255;
+      const T v = pads[static_cast<int64_t>(en.x) * (3 * kPadRow) + a * kPadRow + b + (lane & 7)];
+      raw[j] = valid ? static_cast<double>(v) : 0.0;
+    }
+    const int e = 16 * st + (lane >> 1);
+    const bool valid = lane < 32 && e < it.count;
+    const C<T> gq = g[ent[it.start + (valid ? e : 0)].x];
+    graw = valid ? static_cast<double>((lane & 1) ? gq.im : gq.re) : 0.0;
+  };
+  auto publish = [&](const double* raw, double graw) {
+#pragma unroll
+    for (int j = 0; j < 6; ++j) wts[64 * j + lane] = raw[j];
+    if (lane < 32) gv[lane] = graw;
+  };
+  double raw[6], graw = 0.0;
+  if (nst > 0) {
+    load_stage(0, raw, graw);
+    publish(raw, graw);
+  }
+  __syncthreads();
+  const int k = lane >> 4, i = lane & 15, x = i >> 1, p = i & 1;
+  dbl4s acc[4];
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb) acc[mb] = dbl4s{0.0, 0.0, 0.0, 0.0};
+  for (int st = 0; st < nst; ++st) {
+    const bool more = st + 1 < nst;
+    if (more) load_stage(st + 1, raw, graw);  // in flight during this stage's products
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = 4 * q + k;               // entry of this lane's K index at step q
+      const double* we = wts + e * 24;
+      const double b = we[x] * gv[2 * e + p];
+      const double wzv = we[16 + (i & 7)];
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb)
+        acc[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(we[8 + 2 * mb + (i >> 3)] * wzv, b, acc[mb], 0, 0, 0);
+    }
+    if (more) {
+      __syncthreads();                       // every lane has read this stage's weights
+      publish(raw, graw);
+      __syncthreads();
+    }
+  }
+  // item t of block mb: row 4 t + k -> (y, z) = (2 mb + t / 2, 4 (t % 2) + k), column (x, p)
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int y = 2 * mb + (t >> 1), z = 4 * (t & 1) + k;
+      tileO[x * XS + (y * 8 + z) * 2 + p] = acc[mb][t];
+    }
+  }
+  __syncthreads();
+  // eight lanes per 128-byte row: store r covers columns 8 r .. 8 r + 7, lane & 7 = z
+  const int z = lane & 7;
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const int c = 8 * r + (lane >> 3), cx = c >> 3, cy = c & 7;
+    const double* o = tileO + cx * XS + (cy * 8 + z) * 2;
+    const C<T> v = C<T>{static_cast<T>(o[0]), static_cast<T>(o[1])};
+    if (it.slot < 0)
+      F[(static_cast<int64_t>(tx * 8 + cx) * nf1 + (ty * 8 + cy)) * nf2 + tz * kTileZ + z] = v;
+    else
+      partial[static_cast<int64_t>(it.slot) * 64 * kTileZ + z * 64 + c] = v;
+  }
+}
+
 // ------------------------------------------------------------------ tile-owned interpolation
 __device__ inline int mod_fine(int d, int n) { return d < 0 ? d + n : d; }
 
@@ -718,9 +819,19 @@ static hipError_t spread_t(DevicePlan& P, int which, const C<T>* g, hipStream_t 
   C<T>* F = reinterpret_cast<C<T>*>(P.fine);
   const int nitems = static_cast<int>(S.items.size());
   constexpr bool kahan = sizeof(T) == 4;
-  hipLaunchKernelGGL((k_spread<T, kahan, TX, TY>), dim3(nitems), dim3(64), 0, s, F,
-                     reinterpret_cast<C<T>*>(P.partial), reinterpret_cast<const NodeRec<T>*>(P.nodes), g, D.list,
-                     D.items, H.nf[0], H.nf[1], H.nf[2], H.ntiles[1], H.ntiles[2], H.W[0], H.W[1], H.W[2]);
+  bool done = false;
+  if constexpr (kSpreadMfma && sizeof(T) == 8 && TX == 8) {
+    if (H.padded_rows && P.pads) {
+      hipLaunchKernelGGL((k_spread_mfma<T>), dim3(nitems), dim3(64), 0, s, F, reinterpret_cast<C<T>*>(P.partial),
+                         reinterpret_cast<const T*>(P.pads), g, reinterpret_cast<const int2*>(D.ent), D.items, H.nf[1],
+                         H.nf[2], H.ntiles[1], H.ntiles[2]);
+      done = true;
+    }
+  }
+  if (!done)
+    hipLaunchKernelGGL((k_spread<T, kahan, TX, TY>), dim3(nitems), dim3(64), 0, s, F,
+                       reinterpret_cast<C<T>*>(P.partial), reinterpret_cast<const NodeRec<T>*>(P.nodes), g, D.list,
+                       D.items, H.nf[0], H.nf[1], H.nf[2], H.ntiles[1], H.ntiles[2], H.W[0], H.W[1], H.W[2]);
   DDI_CHECK(hipGetLastError());
   DDI_REC(5);
   if (!S.reduces.empty()) {
