@@ -81,6 +81,9 @@ ddi_status build_device(ddi::DevicePlan& P, hipStream_t s, std::vector<ddi::Node
   HIP_TRY(upload(&P.c_half, cs_half.data(), cs_half.size(), s, bytes), "upload weights");
   for (int a = 0; a < 3; ++a)
     HIP_TRY(upload(&P.deconv[a], H.deconv[a].data(), H.deconv[a].size(), s, bytes), "upload deconvolution");
+  // tile-owned interpolation (FP64 in 3D) and the padded weight rows of the matrix-core kernels
+  const bool tile_interp = ddi::interp_is_tiled(H, sizeof(T) == 8);
+  const bool use_pads = ddi::uses_padded_rows(H);
   for (int w = 0; w < 2; ++w) {
     const ddi::Schedule& S = H.sched[w];
     auto& D = P.dsched[w];
@@ -90,13 +93,13 @@ ddi_status build_device(ddi::DevicePlan& P, hipStream_t s, std::vector<ddi::Node
     HIP_TRY(upload(&D.interp_items, S.interp_items.data(), S.interp_items.size(), s, bytes), "upload interp groups");
     HIP_TRY(upload(&D.interp_direct, S.interp_direct.data(), S.interp_direct.size(), s, bytes),
             "upload interp list");
-    if (ddi::kInterpTile && sizeof(T) == 8 && H.tile[0] == 8) {
+    if (tile_interp) {
       HIP_TRY(upload(&D.gptr, S.gptr.data(), S.gptr.size(), s, bytes), "upload interp gather");
       HIP_TRY(upload(&D.gpos, S.gpos.data(), S.gpos.size(), s, bytes), "upload interp gather");
-      if (H.padded_rows) HIP_TRY(upload(&D.ent, S.ent.data(), S.ent.size(), s, bytes), "upload entry table");
     }
+    if (use_pads) HIP_TRY(upload(&D.ent, S.ent.data(), S.ent.size(), s, bytes), "upload entry table");
   }
-  if (ddi::kInterpTile && sizeof(T) == 8 && H.padded_rows) {
+  if (use_pads) {
     padrows.assign(static_cast<size_t>(H.M) * 3 * ddi::kPadRow, T(0));
     for (int64_t q = 0; q < H.M; ++q)
       for (int a = 0; a < 3; ++a)
@@ -128,7 +131,7 @@ ddi_status build_device(ddi::DevicePlan& P, hipStream_t s, std::vector<ddi::Node
   HIP_TRY(hipMalloc(&P.gnodes, H.M * sizeof(ddi::Complex<T>)), "allocate node values");
   bytes += H.M * static_cast<int64_t>(sizeof(ddi::Complex<T>));
   const size_t nentries = std::max(H.sched[0].list.size(), H.sched[1].list.size());
-  if (nentries > 0 && ddi::kInterpTile && sizeof(T) == 8 && H.tile[0] == 8) {
+  if (nentries > 0 && tile_interp) {
     const int64_t ib = static_cast<int64_t>(nentries) * sizeof(ddi::Complex<double>);
     HIP_TRY(hipMalloc(&P.ipartial, ib), "allocate interpolation partial sums");
     bytes += ib;

@@ -146,6 +146,11 @@ struct HostTables {
   Schedule sched[2];
 };
 
+// Kernel selection shared by the plan upload and the drivers.
+inline bool uses_padded_rows(const HostTables& H) { return H.padded_rows && ((kInterpTile && kInterpMfma) || kSpreadMfma); }
+// (FP64 only: for the FP32 plans' narrower kernel the node-owned interpolation measured faster)
+inline bool interp_is_tiled(const HostTables& H, bool fp64) { return kInterpTile && H.tile[0] == 8 && fp64; }
+
 // Builds every host table of a plan.  Returns an empty string on success or an error message.
 std::string build_tables(const ddi_params& p, HostTables& t, int* status);
 

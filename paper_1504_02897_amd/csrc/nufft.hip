@@ -312,6 +312,15 @@ __global__ void __launch_bounds__(64) k_spread_mfma(C<T>* __restrict__ F, C<T>* 
   const int tz = it.tile % nt2;
   const int ty = (it.tile / nt2) % nt1;
   const int tx = it.tile / (nt2 * nt1);
+  if (it.count == 0) {                       // empty tile (never a chunk): zeros, eight lanes per row
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int c = 8 * r + (lane >> 3);
+      F[(static_cast<int64_t>(tx * 8 + (c >> 3)) * nf1 + (ty * 8 + (c & 7))) * nf2 + tz * kTileZ + (lane & 7)] =
+          C<T>{0, 0};
+    }
+    return;
+  }
   __shared__ double wts[16 * 24];            // [entry of the stage][axis][8 tile positions]
   __shared__ double gv[16 * 2];              // [entry of the stage][part]
   constexpr int XS = 136;                    // x stride of the output staging (bank spread)
@@ -786,9 +795,7 @@ static hipError_t interp_tile_t(DevicePlan& P, int which, C<T>* out, const doubl
 template <typename T>
 static hipError_t interp(DevicePlan& P, int which, C<T>* out, const double* scale, double sscalar,
                          hipStream_t s) {
-  if constexpr (kInterpTile && sizeof(T) == 8) {
-    if (P.H.tile[0] == 8 && P.H.tile[1] == 8) return interp_tile_t<T>(P, which, out, scale, sscalar, s);
-  }
+  if (interp_is_tiled(P.H, sizeof(T) == 8)) return interp_tile_t<T>(P, which, out, scale, sscalar, s);
   {
     switch (P.H.w) {
       case 2: return interp_d<T, 2>(P, which, out, scale, sscalar, s);
@@ -820,7 +827,7 @@ static hipError_t spread_t(DevicePlan& P, int which, const C<T>* g, hipStream_t 
   const int nitems = static_cast<int>(S.items.size());
   constexpr bool kahan = sizeof(T) == 4;
   bool done = false;
-  if constexpr (kSpreadMfma && sizeof(T) == 8 && TX == 8) {
+  if constexpr (kSpreadMfma && TX == 8) {
     if (H.padded_rows && P.pads) {
       hipLaunchKernelGGL((k_spread_mfma<T>), dim3(nitems), dim3(64), 0, s, F, reinterpret_cast<C<T>*>(P.partial),
                          reinterpret_cast<const T*>(P.pads), g, reinterpret_cast<const int2*>(D.ent), D.items, H.nf[1],
