@@ -27,6 +27,16 @@ constexpr int kInterpMinGroup = DDI_INTERP_MIN_GROUP;
 #endif
 // spread: nodes staged in LDS per batch (LDS per wave ~ batch * 26 values)
 constexpr int kSpreadBatch = DDI_SPREAD_BATCH;
+#ifndef DDI_SPREAD_CHUNK
+#define DDI_SPREAD_CHUNK 256
+#endif
+#ifndef DDI_SPREAD_CHUNK_MFMA
+#define DDI_SPREAD_CHUNK_MFMA 512
+#endif
+// spread: a tile with more nodes is split into chunks of this many (partial tiles + reduce);
+// the matrix-core kernels take longer chunks (cheaper per node)
+constexpr int kSpreadChunk = DDI_SPREAD_CHUNK;
+constexpr int kSpreadChunkMfma = DDI_SPREAD_CHUNK_MFMA;
 #ifndef DDI_SPREAD_XCD_ORDER
 #define DDI_SPREAD_XCD_ORDER 0
 #endif

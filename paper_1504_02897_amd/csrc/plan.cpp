@@ -194,7 +194,7 @@ std::string build_spread_schedule(const HostTables& t, const std::vector<int64_t
           }
     }
   }
-  const int chunk = 256;
+  const int chunk = t.padded_rows && kSpreadMfma ? kSpreadChunkMfma : kSpreadChunk;
   S.items.clear();
   S.reduces.clear();
   int32_t slot = 0;
