@@ -321,10 +321,13 @@ __global__ void __launch_bounds__(64) k_spread_mfma(C<T>* __restrict__ F, C<T>* 
     }
     return;
   }
-  __shared__ double wts[16 * 24];            // [entry of the stage][axis][8 tile positions]
-  __shared__ double gv[16 * 2];              // [entry of the stage][part]
+  // one LDS buffer: the stage weights and node values while entries are accumulated, then the
+  // output tile (after the last stage)
   constexpr int XS = 136;                    // x stride of the output staging (bank spread)
-  __shared__ double tileO[8 * XS];           // [x][y][z][part]
+  __shared__ double lds[8 * XS];
+  double* wts = lds;                         // [entry of the stage][axis][8 tile positions]
+  double* gv = lds + 16 * 24;                // [entry of the stage][part]
+  double* tileO = lds;                       // [x][y][z][part]
   const int nst = (it.count + 15) / 16;
   auto load_stage = [&](int st, double* raw, double& graw) {
 #pragma unroll
@@ -376,6 +379,7 @@ __global__ void __launch_bounds__(64) k_spread_mfma(C<T>* __restrict__ F, C<T>* 
       __syncthreads();
     }
   }
+  __syncthreads();                           // the last stage's weights are no longer read
   // item t of block mb: row 4 t + k -> (y, z) = (2 mb + t / 2, 4 (t % 2) + k), column (x, p)
 #pragma unroll
   for (int mb = 0; mb < 4; ++mb) {
