@@ -81,9 +81,9 @@ ddi_status build_device(ddi::DevicePlan& P, hipStream_t s, std::vector<ddi::Node
   HIP_TRY(upload(&P.c_half, cs_half.data(), cs_half.size(), s, bytes), "upload weights");
   for (int a = 0; a < 3; ++a)
     HIP_TRY(upload(&P.deconv[a], H.deconv[a].data(), H.deconv[a].size(), s, bytes), "upload deconvolution");
-  // tile-owned interpolation (FP64 in 3D) and the padded weight rows of the matrix-core kernels
+  // tile-owned interpolation (FP64 in 3D) and the weight rows of the matrix-core kernels
   const bool tile_interp = ddi::interp_is_tiled(H, sizeof(T) == 8);
-  const bool use_pads = ddi::uses_padded_rows(H);
+  const bool use_pads = ddi::uses_weight_rows(H);
   for (int w = 0; w < 2; ++w) {
     const ddi::Schedule& S = H.sched[w];
     auto& D = P.dsched[w];
@@ -100,13 +100,13 @@ ddi_status build_device(ddi::DevicePlan& P, hipStream_t s, std::vector<ddi::Node
     if (use_pads) HIP_TRY(upload(&D.ent, S.ent.data(), S.ent.size(), s, bytes), "upload entry table");
   }
   if (use_pads) {
-    padrows.assign(static_cast<size_t>(H.M) * 3 * ddi::kPadRow, T(0));
+    padrows.assign(static_cast<size_t>(H.M) * 3 * ddi::kRowLen, T(0));
     for (int64_t q = 0; q < H.M; ++q)
       for (int a = 0; a < 3; ++a)
         for (int i = 0; i < ddi::kWMax; ++i)
-          padrows[(q * 3 + a) * ddi::kPadRow + ddi::kPadOff + i] = static_cast<T>(H.wts[(q * 3 + a) * ddi::kWMax + i]);
+          padrows[(q * 3 + a) * ddi::kRowLen + i] = static_cast<T>(H.wts[(q * 3 + a) * ddi::kWMax + i]);
     T* dp = nullptr;
-    HIP_TRY(upload(&dp, padrows.data(), padrows.size(), s, bytes), "upload padded weight rows");
+    HIP_TRY(upload(&dp, padrows.data(), padrows.size(), s, bytes), "upload weight rows");
     P.pads = dp;
   }
   // twiddles for every FFT length used: fine grid sizes and the unpadded sizes

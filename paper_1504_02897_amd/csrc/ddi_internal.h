@@ -43,8 +43,8 @@ constexpr int kSpreadChunkMfma = DDI_SPREAD_CHUNK_MFMA;
 #ifndef DDI_SPREAD_UNROLL
 #define DDI_SPREAD_UNROLL 4
 #endif
-constexpr int kPadRow = 32;       // zero-padded weight row: 8 zeros, the w weights, zeros
-constexpr int kPadOff = 8;
+constexpr int kRowLen = kWMax;    // weight row of the matrix-core kernels: w weights, then zeros
+constexpr int kOffBias = 8;       // entry offsets are stored biased by this (non-negative bytes)
 #ifndef DDI_INTERP_TILE
 #define DDI_INTERP_TILE 1
 #endif
@@ -55,12 +55,12 @@ constexpr bool kInterpTile = DDI_INTERP_TILE != 0;
 #ifndef DDI_INTERP_MFMA
 #define DDI_INTERP_MFMA 1
 #endif
-// tile-owned FP64 interpolation on the matrix cores where the plan has padded weight rows
+// tile-owned FP64 interpolation on the matrix cores where the plan has row windows
 constexpr bool kInterpMfma = DDI_INTERP_MFMA != 0;
 #ifndef DDI_SPREAD_MFMA
 #define DDI_SPREAD_MFMA 1
 #endif
-// FP64 spread on the matrix cores where the plan has padded weight rows
+// spread on the matrix cores where the plan has row windows
 constexpr bool kSpreadMfma = DDI_SPREAD_MFMA != 0;
 
 // One quadrature node as seen by the spread / interpolation kernels: the first
@@ -111,8 +111,8 @@ struct Schedule {
   // are gpos[gptr[q] .. gptr[q+1]) (increasing)
   std::vector<int32_t> gptr;
   std::vector<int32_t> gpos;
-  // padded-row form (see HostTables::padded_rows): per list entry i, ent[2i] = node and
-  // ent[2i+1] = kPadOff + s_a packed as bytes x | y << 8 | z << 16, where s_a in [-7, w-1]
+  // row-window form (see HostTables::row_windows): per list entry i, ent[2i] = node and
+  // ent[2i+1] = kOffBias + s_a packed as bytes x | y << 8 | z << 16, where s_a in [-7, w-1]
   // is the tile origin minus the support origin on axis a
   std::vector<int32_t> ent;
 };
@@ -151,13 +151,13 @@ struct HostTables {
   // was masked out, 0 for the partner that is not kept in the half set
   std::vector<double> half_factor;
   // 3D with 8 x 8 x 8 tiles and n_fine >= w + 8 on every axis: a node's weights at a tile's
-  // positions are one contiguous run of a zero-padded row (no periodic wrap inside a tile)
-  bool padded_rows = false;
+  // positions are one contiguous run of its weight row (no periodic wrap inside a tile)
+  bool row_windows = false;
   Schedule sched[2];
 };
 
 // Kernel selection shared by the plan upload and the drivers.
-inline bool uses_padded_rows(const HostTables& H) { return H.padded_rows && ((kInterpTile && kInterpMfma) || kSpreadMfma); }
+inline bool uses_weight_rows(const HostTables& H) { return H.row_windows && ((kInterpTile && kInterpMfma) || kSpreadMfma); }
 // (FP64 only: for the FP32 plans' narrower kernel the node-owned interpolation measured faster)
 inline bool interp_is_tiled(const HostTables& H, bool fp64) { return kInterpTile && H.tile[0] == 8 && fp64; }
 
@@ -215,7 +215,7 @@ struct DevicePlan {
   void* gnodes = nullptr;        // Complex<T>[M]
   void* partial = nullptr;       // Complex<T>[nslots][tile volume]
   void* ipartial = nullptr;      // Complex<double>[spread entries]: interpolation partial sums
-  void* pads = nullptr;          // T[M][3][kPadRow]: zero-padded weight rows
+  void* pads = nullptr;          // T[M][3][kRowLen]: weight rows, one 128-byte line per row in FP64
   int64_t workspace_bytes = 0;
   // GPE workspace (allocated on first use)
   void* gpe_rho = nullptr;       // T[N]

@@ -290,13 +290,13 @@ __global__ void __launch_bounds__(64) k_spread(C<T>* __restrict__ F, C<T>* __res
   }
 }
 
-// Matrix-core form of the spread (FP64, 3D, padded weight rows): for a tile
+// Matrix-core form of the spread (FP64, 3D, weight rows): for a tile
 //   D[(y,z)][(x,p)] = sum_e A[e][(y,z)] Bs[e][(x,p)],  A[e][(y,z)] = wy_e[y] wz_e[z],
 //   Bs[e][(x,p)] = wx_e[x] (part p of g_e),
 // with K = entries (four per v_mfma_f64_16x16x4f64 step), four 16-row blocks of (y,z) rows
 // and N = (x, p): the whole tile accumulates in registers.  The weights and node values of
 // each stage of 16 entries are loaded cooperatively (eight lanes per contiguous run of a
-// padded row) and published through LDS, the next stage's loads in flight during the
+// weight row) and published through LDS, the next stage's loads in flight during the
 // current stage's products.  The tile goes through LDS and is written eight lanes per row
 // along the last axis (or to its partial slot, in k_spread's slot layout).
 template <typename T>
@@ -336,9 +336,11 @@ __global__ void __launch_bounds__(64) k_spread_mfma(C<T>* __restrict__ F, C<T>* 
       const int e = 16 * st + w / 3, a = w % 3;
       const bool valid = e < it.count;
       const int2 en = ent[it.start + (valid ? e : 0)];
-      const int b = (en.y >> (8 * a)) & 255;
-      const T v = pads[static_cast<int64_t>(en.x) * (3 * kPadRow) + a * kPadRow + b + (lane & 7)];
-      raw[j] = valid ? static_cast<double>(v) : 0.0;
+      // tile position lane & 7 is support index s + (lane & 7); outside the row: zero
+      const int d = ((en.y >> (8 * a)) & 255) - kOffBias + (lane & 7);
+      const bool in = valid && d >= 0 && d < kRowLen;
+      const T v = pads[static_cast<int64_t>(en.x) * (3 * kRowLen) + a * kRowLen + (in ? d : 0)];
+      raw[j] = in ? static_cast<double>(v) : 0.0;
     }
     const int e = 16 * st + (lane >> 1);
     const bool valid = lane < 32 && e < it.count;
@@ -485,7 +487,7 @@ __global__ void __launch_bounds__(64) k_interp_col(const C<T>* __restrict__ F, c
   }
 }
 
-// Matrix-core form of the same tile interpolation (FP64, 3D, padded weight rows).  For the
+// Matrix-core form of the same tile interpolation (FP64, 3D, weight rows).  For the
 // entries of a tile the partials are a dense product followed by a short weighting:
 //   G[e][(x,p)] = sum_{(y,z)} A[e][(y,z)] B[(y,z)][(x,p)],  A[e][(y,z)] = wy_e[y] wz_e[z],
 //   B[(y,z)][(x,p)] = part p (re, im) of F[x][y][z],           partial_e,p = sum_x wx_e[x] G[e][(x,p)].
@@ -495,7 +497,7 @@ __global__ void __launch_bounds__(64) k_interp_col(const C<T>* __restrict__ F, c
 // covers y = 4 (k / 2) + s / 4, z = 4 (k % 2) + s % 4, so a lane needs four y and four z
 // weights of its entry.  B is staged in LDS once per item in fragment order (each lane reads
 // its own element); the weights of a row block are loaded cooperatively (eight lanes per
-// contiguous run of a padded row) and published through LDS, their loads pipelined across
+// contiguous run of a weight row) and published through LDS, their loads pipelined across
 // the blocks' matrix products.
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
@@ -515,9 +517,9 @@ __global__ void __launch_bounds__(64) k_interp_mfma(const C<T>* __restrict__ F, 
   __shared__ double wts[16 * 24];            // [entry of the block][axis][8 tile positions]
   const int nmb = (it.count + 15) / 16;
   // Weights of a row block are loaded cooperatively: load j covers windows 8 j .. 8 j + 7
-  // (window w = entry w / 3, axis w % 3), eight lanes per contiguous run of a padded row.
+  // (window w = entry w / 3, axis w % 3), eight lanes per contiguous run of a weight row.
   // The two dependent loads are pipelined across blocks: entry records two blocks ahead,
-  // padded rows one block ahead.
+  // weight rows one block ahead.
   auto load_ent = [&](int mb, int2* en) {
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
@@ -530,9 +532,11 @@ __global__ void __launch_bounds__(64) k_interp_mfma(const C<T>* __restrict__ F, 
     for (int j = 0; j < 6; ++j) {
       const int w = 8 * j + (lane >> 3);
       const int e = 16 * mb + w / 3, a = w % 3;
-      const int b = (en[j].y >> (8 * a)) & 255;
-      const T v = pads[static_cast<int64_t>(en[j].x) * (3 * kPadRow) + a * kPadRow + b + (lane & 7)];
-      raw[j] = e < it.count ? static_cast<double>(v) : 0.0;
+      // tile position lane & 7 is support index s + (lane & 7); outside the row: zero
+      const int d = ((en[j].y >> (8 * a)) & 255) - kOffBias + (lane & 7);
+      const bool in = e < it.count && d >= 0 && d < kRowLen;
+      const T v = pads[static_cast<int64_t>(en[j].x) * (3 * kRowLen) + a * kRowLen + (in ? d : 0)];
+      raw[j] = in ? static_cast<double>(v) : 0.0;
     }
   };
   int2 en_a[6], en_b[6];
@@ -777,7 +781,7 @@ static hipError_t interp_tile_t(DevicePlan& P, int which, C<T>* out, const doubl
   const DevicePlan::DevSchedule& D = P.dsched[which];
   const int nitems = static_cast<int>(S.items.size());
   if (nitems > 0 && !S.list.empty()) {
-    if (kInterpMfma && H.padded_rows)
+    if (kInterpMfma && H.row_windows)
       hipLaunchKernelGGL((k_interp_mfma<T>), dim3(nitems), dim3(64), 0, s, reinterpret_cast<const C<T>*>(P.fine),
                          reinterpret_cast<const T*>(P.pads), reinterpret_cast<const int2*>(D.ent), D.items, H.nf[1],
                          H.nf[2], H.ntiles[1], H.ntiles[2], reinterpret_cast<C<double>*>(P.ipartial));
@@ -832,7 +836,7 @@ static hipError_t spread_t(DevicePlan& P, int which, const C<T>* g, hipStream_t 
   constexpr bool kahan = sizeof(T) == 4;
   bool done = false;
   if constexpr (kSpreadMfma && TX == 8) {
-    if (H.padded_rows && P.pads) {
+    if (H.row_windows && P.pads) {
       hipLaunchKernelGGL((k_spread_mfma<T>), dim3(nitems), dim3(64), 0, s, F, reinterpret_cast<C<T>*>(P.partial),
                          reinterpret_cast<const T*>(P.pads), g, reinterpret_cast<const int2*>(D.ent), D.items, H.nf[1],
                          H.nf[2], H.ntiles[1], H.ntiles[2]);

@@ -194,7 +194,7 @@ std::string build_spread_schedule(const HostTables& t, const std::vector<int64_t
           }
     }
   }
-  const int chunk = t.padded_rows && kSpreadMfma ? kSpreadChunkMfma : kSpreadChunk;
+  const int chunk = t.row_windows && kSpreadMfma ? kSpreadChunkMfma : kSpreadChunk;
   S.items.clear();
   S.reduces.clear();
   int32_t slot = 0;
@@ -222,9 +222,9 @@ std::string build_spread_schedule(const HostTables& t, const std::vector<int64_t
                    [](const SpreadItem& x, const SpreadItem& y) { return x.count > y.count; });
 #endif
   S.nslots = slot;
-  // padded-row offsets of every (tile, node) entry
+  // weight-row offsets of every (tile, node) entry
   S.ent.clear();
-  if (t.padded_rows) {
+  if (t.row_windows) {
     S.ent.assign(2 * S.list.size(), 0);
     for (int64_t tid = 0; tid < ntile_total; ++tid) {
       const int64_t org[3] = {(tid / (static_cast<int64_t>(t.ntiles[2]) * t.ntiles[1])) * t.tile[0],
@@ -236,8 +236,8 @@ std::string build_spread_schedule(const HostTables& t, const std::vector<int64_t
           int64_t d = (org[a] - t.l0[3 * q + a]) % t.nf[a];
           if (d < 0) d += t.nf[a];
           if (d > t.nf[a] - t.tile[a]) d -= t.nf[a];     // the tile starts before the support
-          if (d < -(t.tile[a] - 1) || d > t.W[a] - 1) return "entry offset outside the padded row";
-          packed |= static_cast<int32_t>(kPadOff + d) << (8 * a);
+          if (d < -(t.tile[a] - 1) || d > t.W[a] - 1) return "entry offset outside the weight row";
+          packed |= static_cast<int32_t>(kOffBias + d) << (8 * a);
         }
         S.ent[2 * i] = q;
         S.ent[2 * i + 1] = packed;
@@ -505,8 +505,8 @@ std::string build_tables(const ddi_params& p, HostTables& t, int* status) {
     std::stable_sort(tile_order.begin(), tile_order.end(),
                      [&](int64_t x, int64_t y) { return tkey[x] < tkey[y]; });
   }
-  t.padded_rows = t.dim == 3;
-  for (int a = 0; a < 3; ++a) t.padded_rows = t.padded_rows && t.tile[a] == 8 && t.nf[a] >= t.W[a] + 8;
+  t.row_windows = t.dim == 3;
+  for (int a = 0; a < 3; ++a) t.row_windows = t.row_windows && t.tile[a] == 8 && t.nf[a] >= t.W[a] + 8;
   for (int which = 0; which < 2; ++which) {
     Schedule& S = t.sched[which];
     auto used = [&](int64_t s2) { return which == kAll || t.half_factor[s2] > 0.0; };
