@@ -113,6 +113,35 @@ def test_c1_type1_fp64_random_nodes():
     assert err < FP64_TOL
 
 
+@pytest.mark.parametrize("n,tol,w,bound", [(16, 1e-13, 14, FP64_TOL), (8, 1e-7, 8, 1e-6)])
+def test_smallest_grids_fp64(n, tol, w, bound):
+    """Smallest grids the plan accepts: 16^3 at the FP64 width (w = 14, fine grid 32 = the
+    minimum 2w) and 8^3, the minimum size, at w = 8 (fine grid 16 = 2w = w + tile, so the
+    tile windows into a node's weights reach both ends of the fine axis).  Apply, type-2 and
+    type-1 against the oracle; the bound at w = 8 follows the NUFFT tolerance it was planned for."""
+    say(f"case: {n}^3 fp64 tol {tol:g}")
+    L = (3.0, 3.0, 3.0)
+    plan, prob = make(3, (n, n, n), L, (10, 6, 12), dip_n=(0.6, 0.0, 0.8), tol=tol)
+    assert plan.info["n_fine"][0] == 2 * n and plan.info["width"] == w
+    rho = np.abs(I.random_field(11, (n, n, n))) + 0.1
+    phi = plan.apply(to_dev(rho, torch.float64)).cpu().numpy()
+    err = relinf(phi, O.ddi_apply(rho, prob))
+    say(f"  apply rel Linf = {err:.3e}")
+    assert err < bound
+    rows, quad, _ = oracle_rows(plan, prob)
+    rh = plan.type2(to_dev(rho, torch.float64)).cpu().numpy()
+    ref = O.rhohat(rho, prob, quad.k[rows])
+    err2 = float(np.max(np.abs(rh - ref)) / np.max(np.abs(ref)))
+    say(f"  type2 rel Linf = {err2:.3e}")
+    assert err2 < bound
+    rng = np.random.default_rng(5)
+    g = rng.standard_normal(plan.m_eff) + 1j * rng.standard_normal(plan.m_eff)
+    phi1 = plan.type1(to_dev(g, torch.complex128)).cpu().numpy()
+    err1 = relinf(phi1, O.nodes_to_grid(g, prob, quad.k[rows]))
+    say(f"  type1 rel Linf = {err1:.3e}")
+    assert err1 < bound
+
+
 def test_anisotropic_grid_two_axes_fp64():
     """Different N and L per axis (h_x != h_y != h_z) and n != m (Eq. dipmn)."""
     say("case: 16x32x64 anisotropic, n != m, fp64")
