@@ -100,7 +100,7 @@ ddi_status build_device(ddi::DevicePlan& P, hipStream_t s, std::vector<ddi::Node
     if (use_pads) HIP_TRY(upload(&D.ent, S.ent.data(), S.ent.size(), s, bytes), "upload entry table");
   }
   if (use_pads) {
-    padrows.assign(static_cast<size_t>(H.M) * 3 * ddi::kRowLen, T(0));
+    padrows.assign(static_cast<size_t>(H.M + 1) * 3 * ddi::kRowLen, T(0));   // + the zero record
     for (int64_t q = 0; q < H.M; ++q)
       for (int a = 0; a < 3; ++a)
         for (int i = 0; i < ddi::kWMax; ++i)

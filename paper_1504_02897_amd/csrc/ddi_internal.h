@@ -45,6 +45,7 @@ constexpr int kSpreadChunkMfma = DDI_SPREAD_CHUNK_MFMA;
 #endif
 constexpr int kRowLen = kWMax;    // weight row of the matrix-core kernels: w weights, then zeros
 constexpr int kOffBias = 8;       // entry offsets are stored biased by this (non-negative bytes)
+constexpr int kEntPad = 32;       // zero entries after the last one (blocks of 16 may read past an item)
 #ifndef DDI_INTERP_TILE
 #define DDI_INTERP_TILE 1
 #endif
@@ -113,7 +114,7 @@ struct Schedule {
   std::vector<int32_t> gpos;
   // row-window form (see HostTables::row_windows): per list entry i, ent[2i] = node and
   // ent[2i+1] = kOffBias + s_a packed as bytes x | y << 8 | z << 16, where s_a in [-7, w-1]
-  // is the tile origin minus the support origin on axis a
+  // is the tile origin minus the support origin on axis a; kEntPad zero entries follow
   std::vector<int32_t> ent;
 };
 
@@ -151,7 +152,8 @@ struct HostTables {
   // was masked out, 0 for the partner that is not kept in the half set
   std::vector<double> half_factor;
   // 3D with 8 x 8 x 8 tiles and n_fine >= w + 8 on every axis: a node's weights at a tile's
-  // positions are one contiguous run of its weight row (no periodic wrap inside a tile)
+  // positions are one contiguous run of its weight row (no periodic wrap inside a tile); and
+  // the weight rows fit 32-bit byte offsets (2 GiB)
   bool row_windows = false;
   Schedule sched[2];
 };
@@ -215,7 +217,8 @@ struct DevicePlan {
   void* gnodes = nullptr;        // Complex<T>[M]
   void* partial = nullptr;       // Complex<T>[nslots][tile volume]
   void* ipartial = nullptr;      // Complex<double>[spread entries]: interpolation partial sums
-  void* pads = nullptr;          // T[M][3][kRowLen]: weight rows, one 128-byte line per row in FP64
+  void* pads = nullptr;          // T[M + 1][3][kRowLen]: weight rows (one 128-byte line per row in
+                                 // FP64), then a zero record that positions outside a window read
   int64_t workspace_bytes = 0;
   // GPE workspace (allocated on first use)
   void* gpe_rho = nullptr;       // T[N]

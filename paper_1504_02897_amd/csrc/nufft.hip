@@ -290,6 +290,56 @@ __global__ void __launch_bounds__(64) k_spread(C<T>* __restrict__ F, C<T>* __res
   }
 }
 
+// Cooperative weight loads of the matrix-core kernels.  For a block of 16 (tile, node)
+// entries, load j (0..5) covers window w = 8 j + (lane >> 3) -- entry w / 3, axis w % 3 -- at
+// tile position t = lane & 7, so eight lanes read one contiguous run of a weight row.  The
+// entry records and weight rows are read as raw buffers: a lane offset (32-bit) plus the
+// block's uniform offset, with no per-lane 64-bit address arithmetic.  The entry table ends
+// with kEntPad zero records, so a block may run past its item's entries; positions outside
+// the node's weight row read the zero record at byte offset zrec of the rows.
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+constexpr int kBufferWord3 = 0x00020000;     // raw buffer descriptor word 3 (32-bit data, no swizzle)
+
+template <typename X>
+__device__ inline __amdgpu_buffer_rsrc_t raw_buffer(const X* p, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<X*>(p), 0, static_cast<int>(bytes), kBufferWord3);
+}
+
+struct CoopLanes {
+  unsigned eo[6];                            // byte offset of the window's entry record in the block
+  int sh[6];                                 // 8 * axis: bit offset of the axis's packed window start
+  int tb;                                    // t - kOffBias
+  __device__ explicit CoopLanes(int lane) {
+    tb = (lane & 7) - kOffBias;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const int w = 8 * j + (lane >> 3);
+      eo[j] = static_cast<unsigned>(w / 3) * sizeof(int2);
+      sh[j] = 8 * (w % 3);
+    }
+  }
+  // entry record of load j; blk = byte offset of the block's first record
+  __device__ int2 entry(__amdgpu_buffer_rsrc_t ent, int blk, int j) const {
+    return __builtin_bit_cast(int2, __builtin_amdgcn_raw_buffer_load_b64(ent, eo[j], blk, 0));
+  }
+  // byte offset in the weight rows of load j's position for entry record en
+  template <typename T>
+  __device__ unsigned row_offset(int2 en, int j, unsigned zrec) const {
+    const int d = ((en.y >> sh[j]) & 255) + tb;  // support index of this tile position
+    const unsigned at = __umul24(static_cast<unsigned>(en.x), 3 * kRowLen) + static_cast<unsigned>(d + 2 * sh[j]);
+    const unsigned off = at * static_cast<unsigned>(sizeof(T));
+    return static_cast<unsigned>(d) < static_cast<unsigned>(kRowLen) ? off : zrec;
+  }
+};
+
+template <typename T>
+__device__ inline double row_load(__amdgpu_buffer_rsrc_t rows, unsigned off) {
+  if constexpr (sizeof(T) == 8)
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rows, off, 0, 0));
+  else
+    return static_cast<double>(__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rows, off, 0, 0)));
+}
+
 // Matrix-core form of the spread (FP64, 3D, weight rows): for a tile
 //   D[(y,z)][(x,p)] = sum_e A[e][(y,z)] Bs[e][(x,p)],  A[e][(y,z)] = wy_e[y] wz_e[z],
 //   Bs[e][(x,p)] = wx_e[x] (part p of g_e),
@@ -304,7 +354,7 @@ __global__ void __launch_bounds__(64) k_spread_mfma(C<T>* __restrict__ F, C<T>* 
                                                     const T* __restrict__ pads, const C<T>* __restrict__ g,
                                                     const int2* __restrict__ ent,
                                                     const SpreadItem* __restrict__ items, int nf1, int nf2, int nt1,
-                                                    int nt2) {
+                                                    int nt2, int64_t ent_bytes, int64_t rows_bytes, unsigned zrec) {
   typedef double dbl4s __attribute__((ext_vector_type(4)));
   const int lane = threadIdx.x;
   const SpreadItem it = items[blockIdx.x];
@@ -329,22 +379,21 @@ __global__ void __launch_bounds__(64) k_spread_mfma(C<T>* __restrict__ F, C<T>* 
   double* gv = lds + 16 * 24;                // [entry of the stage][part]
   double* tileO = lds;                       // [x][y][z][part]
   const int nst = (it.count + 15) / 16;
+  // Weights by CoopLanes; entries past the item's count take finite weights (of other
+  // entries, or the zero record) and a zero node value, so they add nothing.
+  const CoopLanes cl(lane);
+  const __amdgpu_buffer_rsrc_t ent_r = raw_buffer(ent, ent_bytes), rows_r = raw_buffer(pads, rows_bytes);
+  const unsigned go = static_cast<unsigned>(lane >> 1) * sizeof(int2);
   auto load_stage = [&](int st, double* raw, double& graw) {
+    const int blk = (it.start + 16 * st) * static_cast<int>(sizeof(int2));
+    int2 en[6];
 #pragma unroll
-    for (int j = 0; j < 6; ++j) {
-      const int w = 8 * j + (lane >> 3);
-      const int e = 16 * st + w / 3, a = w % 3;
-      const bool valid = e < it.count;
-      const int2 en = ent[it.start + (valid ? e : 0)];
-      // tile position lane & 7 is support index s + (lane & 7); outside the row: zero
-      const int d = ((en.y >> (8 * a)) & 255) - kOffBias + (lane & 7);
-      const bool in = valid && d >= 0 && d < kRowLen;
-      const T v = pads[static_cast<int64_t>(en.x) * (3 * kRowLen) + a * kRowLen + (in ? d : 0)];
-      raw[j] = in ? static_cast<double>(v) : 0.0;
-    }
-    const int e = 16 * st + (lane >> 1);
-    const bool valid = lane < 32 && e < it.count;
-    const C<T> gq = g[ent[it.start + (valid ? e : 0)].x];
+    for (int j = 0; j < 6; ++j) en[j] = cl.entry(ent_r, blk, j);
+    const int2 eg = __builtin_bit_cast(int2, __builtin_amdgcn_raw_buffer_load_b64(ent_r, go, blk, 0));
+#pragma unroll
+    for (int j = 0; j < 6; ++j) raw[j] = row_load<T>(rows_r, cl.row_offset<T>(en[j], j, zrec));
+    const bool valid = lane < 32 && 16 * st + (lane >> 1) < it.count;
+    const C<T> gq = g[eg.x];
     graw = valid ? static_cast<double>((lane & 1) ? gq.im : gq.re) : 0.0;
   };
   auto publish = [&](const double* raw, double graw) {
@@ -505,7 +554,8 @@ template <typename T>
 __global__ void __launch_bounds__(64) k_interp_mfma(const C<T>* __restrict__ F, const T* __restrict__ pads,
                                                     const int2* __restrict__ ent,
                                                     const SpreadItem* __restrict__ items, int nf1, int nf2, int nt1,
-                                                    int nt2, C<double>* __restrict__ part) {
+                                                    int nt2, int64_t ent_bytes, int64_t rows_bytes, unsigned zrec,
+                                                    C<double>* __restrict__ part) {
   const int lane = threadIdx.x;
   const SpreadItem it = items[blockIdx.x];
   if (it.tile < 0 || it.count == 0) return;  // padding item or empty tile
@@ -516,45 +566,37 @@ __global__ void __launch_bounds__(64) k_interp_mfma(const C<T>* __restrict__ F, 
   __shared__ double fragB[16 * SB];
   __shared__ double wts[16 * 24];            // [entry of the block][axis][8 tile positions]
   const int nmb = (it.count + 15) / 16;
-  // Weights of a row block are loaded cooperatively: load j covers windows 8 j .. 8 j + 7
-  // (window w = entry w / 3, axis w % 3), eight lanes per contiguous run of a weight row.
-  // The two dependent loads are pipelined across blocks: entry records two blocks ahead,
-  // weight rows one block ahead.
+  // Weights of a row block are loaded cooperatively (CoopLanes).  Entries past the item's
+  // count only fill rows of the product whose results are not stored.  The two dependent
+  // loads are pipelined across blocks: entry records two blocks ahead, weight rows one ahead.
+  const CoopLanes cl(lane);
+  const __amdgpu_buffer_rsrc_t ent_r = raw_buffer(ent, ent_bytes), rows_r = raw_buffer(pads, rows_bytes);
   auto load_ent = [&](int mb, int2* en) {
 #pragma unroll
-    for (int j = 0; j < 6; ++j) {
-      const int e = 16 * mb + (8 * j + (lane >> 3)) / 3;
-      en[j] = ent[it.start + (e < it.count ? e : 0)];
-    }
+    for (int j = 0; j < 6; ++j) en[j] = cl.entry(ent_r, (it.start + 16 * mb) * static_cast<int>(sizeof(int2)), j);
   };
-  auto load_rows = [&](int mb, const int2* en, double* raw) {
+  auto load_rows = [&](const int2* en, double* raw) {
 #pragma unroll
-    for (int j = 0; j < 6; ++j) {
-      const int w = 8 * j + (lane >> 3);
-      const int e = 16 * mb + w / 3, a = w % 3;
-      // tile position lane & 7 is support index s + (lane & 7); outside the row: zero
-      const int d = ((en[j].y >> (8 * a)) & 255) - kOffBias + (lane & 7);
-      const bool in = e < it.count && d >= 0 && d < kRowLen;
-      const T v = pads[static_cast<int64_t>(en[j].x) * (3 * kRowLen) + a * kRowLen + (in ? d : 0)];
-      raw[j] = in ? static_cast<double>(v) : 0.0;
-    }
+    for (int j = 0; j < 6; ++j) raw[j] = row_load<T>(rows_r, cl.row_offset<T>(en[j], j, zrec));
   };
   int2 en_a[6], en_b[6];
   double raw[6];
   load_ent(0, en_a);
   if (nmb > 1) load_ent(1, en_b);
   {
-    // the tile, eight lanes per 128-byte row: load r covers columns 8 r .. 8 r + 7
+    // the tile, eight lanes per 128-byte row: load r covers the row (x, y) = (r, lane / 8)
+    const int cy = lane >> 3, z = lane & 7;
+    const unsigned lo = static_cast<unsigned>(cy * nf2 + z);
+    const int at = (4 * (cy & 3) + (z & 3)) * SB + (2 * (cy >> 2) + (z >> 2)) * 16;
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
-      const int c = 8 * r + (lane >> 3), cx = c >> 3, cy = c & 7, z = lane & 7;
-      const C<T> v = F[(static_cast<int64_t>(tx * 8 + cx) * nf1 + (ty * 8 + cy)) * nf2 + tz * kTileZ + z];
-      const int at = (4 * (cy & 3) + (z & 3)) * SB + (2 * (cy >> 2) + (z >> 2)) * 16 + 2 * cx;
-      fragB[at] = static_cast<double>(v.re);
-      fragB[at + 1] = static_cast<double>(v.im);
+      const C<T>* row = F + (static_cast<int64_t>(tx * 8 + r) * nf1 + ty * 8) * nf2 + tz * kTileZ;
+      const C<T> v = row[lo];
+      fragB[at + 2 * r] = static_cast<double>(v.re);
+      fragB[at + 2 * r + 1] = static_cast<double>(v.im);
     }
   }
-  load_rows(0, en_a, raw);
+  load_rows(en_a, raw);
 #pragma unroll
   for (int j = 0; j < 6; ++j) wts[64 * j + lane] = raw[j];
   __syncthreads();
@@ -572,7 +614,7 @@ __global__ void __launch_bounds__(64) k_interp_mfma(const C<T>* __restrict__ F, 
     // en_b holds block mb + 1's entry records: start its rows, and block mb + 2's records
     const bool more = mb + 1 < nmb;
     if (more) {
-      load_rows(mb + 1, en_b, raw);
+      load_rows(en_b, raw);
 #pragma unroll
       for (int j = 0; j < 6; ++j) en_a[j] = en_b[j];
       if (mb + 2 < nmb) load_ent(mb + 2, en_b);
@@ -603,9 +645,9 @@ __global__ void __launch_bounds__(64) k_interp_mfma(const C<T>* __restrict__ F, 
       r = keep + __shfl_xor(send, 4, 64);
     }
     r += __shfl_xor(r, 2, 64);
-    const int er = 16 * mb + 4 * ((b2 ? 1 : 0) + (b3 ? 2 : 0)) + kk;
-    if ((lane & 2) == 0 && er < it.count)
-      reinterpret_cast<double*>(part + static_cast<int64_t>(it.start) + er)[lane & 1] = r;
+    const int er = 4 * ((b2 ? 1 : 0) + (b3 ? 2 : 0)) + kk;   // entry of the block
+    if ((lane & 2) == 0 && 16 * mb + er < it.count)
+      reinterpret_cast<double*>(part + (static_cast<int64_t>(it.start) + 16 * mb))[2 * er + (lane & 1)] = r;
     if (more) {
       __syncthreads();                       // every lane has read this block's weights
 #pragma unroll
@@ -682,6 +724,18 @@ __global__ void __launch_bounds__(64 * kTileZ) k_spread_reduce(C<T>* __restrict_
 }
 
 // ------------------------------------------------------------------ drivers
+// Sizes of the matrix-core kernels' raw buffers: the entry table and the weight rows (with
+// the zero record that follows them, at byte offset zero_record).
+static int64_t ent_bytes(const Schedule& S) { return static_cast<int64_t>(S.ent.size()) * sizeof(int32_t); }
+template <typename T>
+static unsigned zero_record(const HostTables& H) {
+  return static_cast<unsigned>(H.M * 3 * kRowLen * static_cast<int64_t>(sizeof(T)));
+}
+template <typename T>
+static int64_t rows_bytes(const HostTables& H) {
+  return (H.M + 1) * 3 * kRowLen * static_cast<int64_t>(sizeof(T));
+}
+
 // ev (nullable): events recorded on s at the start (ev[0]) and after each stage:
 // 1 last-axis FFT (pad), 2 axis-1 FFT, 3 axis-0 FFT, 4 interpolation, 5 spread,
 // 6 spread reduce, 7 axis-0 FFT, 8 axis-1 FFT, 9 last-axis FFT (truncate).
@@ -784,7 +838,8 @@ static hipError_t interp_tile_t(DevicePlan& P, int which, C<T>* out, const doubl
     if (kInterpMfma && H.row_windows)
       hipLaunchKernelGGL((k_interp_mfma<T>), dim3(nitems), dim3(64), 0, s, reinterpret_cast<const C<T>*>(P.fine),
                          reinterpret_cast<const T*>(P.pads), reinterpret_cast<const int2*>(D.ent), D.items, H.nf[1],
-                         H.nf[2], H.ntiles[1], H.ntiles[2], reinterpret_cast<C<double>*>(P.ipartial));
+                         H.nf[2], H.ntiles[1], H.ntiles[2], ent_bytes(S), rows_bytes<T>(H), zero_record<T>(H),
+                         reinterpret_cast<C<double>*>(P.ipartial));
     else
       hipLaunchKernelGGL((k_interp_col<T>), dim3(nitems), dim3(64), 0, s, reinterpret_cast<const C<T>*>(P.fine),
                          reinterpret_cast<const NodeRec<T>*>(P.nodes), D.list, D.items, H.nf[0], H.nf[1], H.nf[2],
@@ -839,7 +894,7 @@ static hipError_t spread_t(DevicePlan& P, int which, const C<T>* g, hipStream_t 
     if (H.row_windows && P.pads) {
       hipLaunchKernelGGL((k_spread_mfma<T>), dim3(nitems), dim3(64), 0, s, F, reinterpret_cast<C<T>*>(P.partial),
                          reinterpret_cast<const T*>(P.pads), g, reinterpret_cast<const int2*>(D.ent), D.items, H.nf[1],
-                         H.nf[2], H.ntiles[1], H.ntiles[2]);
+                         H.nf[2], H.ntiles[1], H.ntiles[2], ent_bytes(S), rows_bytes<T>(H), zero_record<T>(H));
       done = true;
     }
   }

@@ -225,7 +225,11 @@ std::string build_spread_schedule(const HostTables& t, const std::vector<int64_t
   // weight-row offsets of every (tile, node) entry
   S.ent.clear();
   if (t.row_windows) {
-    S.ent.assign(2 * S.list.size(), 0);
+    // kEntPad zero entries at the end: a kernel's block of 16 may read past its item's entries
+    // (the kernels address the table with 32-bit byte offsets)
+    if (static_cast<int64_t>(S.list.size() + kEntPad) * 2 * static_cast<int64_t>(sizeof(int32_t)) >= (int64_t(1) << 31))
+      return "spread schedule too large";
+    S.ent.assign(2 * (S.list.size() + kEntPad), 0);
     for (int64_t tid = 0; tid < ntile_total; ++tid) {
       const int64_t org[3] = {(tid / (static_cast<int64_t>(t.ntiles[2]) * t.ntiles[1])) * t.tile[0],
                               ((tid / t.ntiles[2]) % t.ntiles[1]) * t.tile[1], (tid % t.ntiles[2]) * t.tile[2]};
@@ -505,7 +509,8 @@ std::string build_tables(const ddi_params& p, HostTables& t, int* status) {
     std::stable_sort(tile_order.begin(), tile_order.end(),
                      [&](int64_t x, int64_t y) { return tkey[x] < tkey[y]; });
   }
-  t.row_windows = t.dim == 3;
+  // (the matrix-core kernels address the weight rows with 32-bit byte offsets)
+  t.row_windows = t.dim == 3 && (t.M + 1) * 3 * kRowLen * static_cast<int64_t>(sizeof(double)) < (int64_t(1) << 31);
   for (int a = 0; a < 3; ++a) t.row_windows = t.row_windows && t.tile[a] == 8 && t.nf[a] >= t.W[a] + 8;
   for (int which = 0; which < 2; ++which) {
     Schedule& S = t.sched[which];
