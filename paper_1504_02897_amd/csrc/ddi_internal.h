@@ -46,6 +46,7 @@ constexpr int kSpreadChunkMfma = DDI_SPREAD_CHUNK_MFMA;
 constexpr int kRowLen = kWMax;    // weight row of the matrix-core kernels: w weights, then zeros
 constexpr int kOffBias = 8;       // entry offsets are stored biased by this (non-negative bytes)
 constexpr int kEntPad = 32;       // zero entries after the last one (blocks of 16 may read past an item)
+constexpr int kZAlign = 16;       // granularity of the last-axis window of a schedule
 #ifndef DDI_INTERP_TILE
 #define DDI_INTERP_TILE 1
 #endif
@@ -116,6 +117,11 @@ struct Schedule {
   // ent[2i+1] = kOffBias + s_a packed as bytes x | y << 8 | z << 16, where s_a in [-7, w-1]
   // is the tile origin minus the support origin on axis a; kEntPad zero entries follow
   std::vector<int32_t> ent;
+  // Last-axis window: every fine position that a scheduled node's support touches lies in
+  // [z0, z0 + nz) (mod n_fine[2]); z0 and nz are multiples of kZAlign.  The FFT passes of
+  // this schedule read and write only the window, and the spread writes only its tiles.
+  int32_t z0 = 0;
+  int32_t nz = 0;
 };
 
 // The two node subsets a plan schedules.  kAll: every node (the type-2 / type-1 entry

@@ -14,16 +14,20 @@ enum ContigMode { R2C_PAD = 0, C2C = 1, C2R_TRUNC = 2 };
 // In-place transforms of length n along axis 0 or 1 of a [d0][d1][d2] complex
 // array.  The other non-last axis runs over n_o lines (the compact modes of an
 // oversampled axis when o_compact); in_c / out_c: only the nc active positions
-// of each line are read / written (exp(SIGN 2 pi i jk/n)).
+// of each line are read / written (exp(SIGN 2 pi i jk/n)).  Only the lines at
+// last-axis positions [z0, z0 + nz) (mod d2) are transformed: z0 and nz are
+// multiples of kZAlign, or z0 = 0 and nz = d2.
 template <typename T, int SIGN>
 hipError_t launch_strided(int n, Complex<T>* F, int axis, int d0, int d1, int d2, int n_o, int o_compact, int nc,
-                          int in_c, int out_c, const Complex<T>* tw, hipStream_t s);
+                          int in_c, int out_c, int z0, int nz, const Complex<T>* tw, hipStream_t s);
 
 // Transforms of length n along the last axis; lines run over the n0 x n1 compact
 // grid (R2C_PAD, C2R_TRUNC: mapped into a [d0][d1][n] oversampled array) or over
-// d0 x d1 = n0 x n1 directly (C2C).
+// d0 x d1 = n0 x n1 directly (C2C).  Only the positions [z0, z0 + nz) (mod n) of
+// the complex lines are written (R2C_PAD) or read, the rest taken as zero
+// (C2R_TRUNC, C2C); z0 = 0 and nz = n: the whole line.
 template <typename T, int SIGN, int MODE>
-hipError_t launch_contig(int n, const void* in, void* out, int n0, int n1, int d0, int d1, int nc2,
+hipError_t launch_contig(int n, const void* in, void* out, int n0, int n1, int d0, int d1, int nc2, int z0, int nz,
                          const double* D0, const double* D1, const double* D2, const Complex<T>* tw,
                          hipStream_t s);
 

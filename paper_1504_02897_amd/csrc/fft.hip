@@ -7,6 +7,7 @@
 // half of the oversampled line.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <type_traits>
 
@@ -211,17 +212,17 @@ __device__ __forceinline__ int cmap(int k, int n, int nc) { return k < nc - nc /
 template <typename T, int N, int SIGN, int MAXT>
 __global__ void __launch_bounds__(MAXT) k_fft_strided(C<T>* __restrict__ F, int axis, int d0, int d1, int d2,
                                                      int n_o, int o_compact, int nc_axis, int in_compact,
-                                                     int out_compact, const C<T>* __restrict__ tw, int B) {
+                                                     int out_compact, int z0, int nzb,
+                                                     const C<T>* __restrict__ tw, int B) {
   extern __shared__ unsigned char smem_raw[];
   LdsElem<T, N>* lds = reinterpret_cast<LdsElem<T, N>*>(smem_raw);
   using P = Radix<T, N, false>;
   constexpr int TL = N / P::R1;
   const int b = threadIdx.x % B;
   const int j0 = threadIdx.x / B;
-  const int zblocks = d2 / B;
   const int blk = blockIdx.x;
-  const int o = blk / zblocks;
-  const int z = (blk % zblocks) * B + b;
+  const int o = blk / nzb;
+  const int z = (z0 + (blk % nzb) * B) % d2 + b;   // z0 is a multiple of B
   const int d_o = axis == 0 ? d1 : d0;
   const int of = o_compact ? fmap(o, d_o, n_o) : o;
   int64_t base, stride;
@@ -254,7 +255,7 @@ __global__ void __launch_bounds__(MAXT) k_fft_strided(C<T>* __restrict__ F, int 
 // Re(line[fmap(c2)]) times the deconvolution factors into phi[N0][N1][N2].
 template <typename T, int N, int SIGN, int MODE>
 __global__ void __launch_bounds__(256) k_fft_contig(const void* in, void* out,
-                                                    int n0, int n1, int d0, int d1, int nc2,
+                                                    int n0, int n1, int d0, int d1, int nc2, int z0, int nz,
                                                     const double* __restrict__ D0, const double* __restrict__ D1,
                                                     const double* __restrict__ D2,
                                                     const C<T>* __restrict__ tw, int B, int nlines) {
@@ -294,7 +295,7 @@ __global__ void __launch_bounds__(256) k_fft_contig(const void* in, void* out,
 #pragma unroll
     for (int r = 0; r < P::R1; ++r) {
       const int k = j0 + r * TL;
-      v[r] = valid ? F[lbase + k] : C<T>{0, 0};
+      v[r] = valid && ((k - z0) & (N - 1)) < nz ? F[lbase + k] : C<T>{0, 0};
     }
   }
   line_fft<T, N, SIGN, P>(my, addr, j0, tw, v);
@@ -317,53 +318,62 @@ __global__ void __launch_bounds__(256) k_fft_contig(const void* in, void* out,
     if (MODE == C2C) lbase = static_cast<int64_t>(line) * N;
     else lbase = (static_cast<int64_t>(fmap(o0, d0, n0)) * d1 + fmap(o1, d1, n1)) * N;
 #pragma unroll
-    for (int i = 0; i < P::R1; ++i) F[lbase + LineOut<P, N>::k(j0, i)] = v[i];
+    for (int i = 0; i < P::R1; ++i) {
+      const int k = LineOut<P, N>::k(j0, i);
+      if (((k - z0) & (N - 1)) < nz) F[lbase + k] = v[i];
+    }
   }
 }
 
 // ------------------------------------------------------------------ dispatch
 template <typename T, int N, int SIGN>
 static hipError_t launch_strided_n(C<T>* F, int axis, int d0, int d1, int d2, int n_o, int o_compact, int nc,
-                                   int in_c, int out_c, const C<T>* tw, hipStream_t s) {
+                                   int in_c, int out_c, int z0, int nz, const C<T>* tw, hipStream_t s) {
   constexpr int TL = N / Radix<T, N, false>::R1;
   // lines per workgroup: at least 256 threads, and row segments of >= 128 B along the
-  // contiguous axis (coalescing) as far as 1024 threads and 64 KB of LDS allow
+  // contiguous axis (coalescing) as far as 1024 threads and 64 KB of LDS allow; a window
+  // of the last axis is covered in blocks of at most kZAlign lines
   int B = 256 / TL;
   while (B * static_cast<int>(sizeof(C<T>)) < 128 && 2 * B * TL <= 1024 &&
          static_cast<size_t>(2 * B) * N * sizeof(LdsElem<T, N>) <= 65536)
     B *= 2;
+  if (nz < d2) B = std::min(B, kZAlign);
   while (B > d2) B >>= 1;
+  if (z0 % B != 0 || nz % B != 0 || nz > d2 || z0 < 0 || z0 >= d2) return hipErrorInvalidValue;
   const size_t shm = static_cast<size_t>(B) * N * sizeof(LdsElem<T, N>);
-  const int blocks = n_o * (d2 / B);
+  const int nzb = nz / B;
+  const int blocks = n_o * nzb;
+  if (blocks == 0) return hipSuccess;
   if (B * TL <= 256)
     hipLaunchKernelGGL((k_fft_strided<T, N, SIGN, 256>), dim3(blocks), dim3(B * TL), shm, s, F, axis, d0, d1, d2,
-                       n_o, o_compact, nc, in_c, out_c, tw, B);
+                       n_o, o_compact, nc, in_c, out_c, z0, nzb, tw, B);
   else
     hipLaunchKernelGGL((k_fft_strided<T, N, SIGN, 1024>), dim3(blocks), dim3(B * TL), shm, s, F, axis, d0, d1, d2,
-                       n_o, o_compact, nc, in_c, out_c, tw, B);
+                       n_o, o_compact, nc, in_c, out_c, z0, nzb, tw, B);
   return hipGetLastError();
 }
 
 template <typename T, int SIGN>
 hipError_t launch_strided(int n, C<T>* F, int axis, int d0, int d1, int d2, int n_o, int o_compact, int nc,
-                                 int in_c, int out_c, const C<T>* tw, hipStream_t s) {
+                                 int in_c, int out_c, int z0, int nz, const C<T>* tw, hipStream_t s) {
   switch (n) {
-    case 8: return launch_strided_n<T, 8, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, tw, s);
-    case 16: return launch_strided_n<T, 16, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, tw, s);
-    case 32: return launch_strided_n<T, 32, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, tw, s);
-    case 64: return launch_strided_n<T, 64, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, tw, s);
-    case 128: return launch_strided_n<T, 128, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, tw, s);
-    case 256: return launch_strided_n<T, 256, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, tw, s);
-    case 512: return launch_strided_n<T, 512, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, tw, s);
-    case 1024: return launch_strided_n<T, 1024, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, tw, s);
+    case 8: return launch_strided_n<T, 8, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, z0, nz, tw, s);
+    case 16: return launch_strided_n<T, 16, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, z0, nz, tw, s);
+    case 32: return launch_strided_n<T, 32, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, z0, nz, tw, s);
+    case 64: return launch_strided_n<T, 64, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, z0, nz, tw, s);
+    case 128: return launch_strided_n<T, 128, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, z0, nz, tw, s);
+    case 256: return launch_strided_n<T, 256, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, z0, nz, tw, s);
+    case 512: return launch_strided_n<T, 512, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, z0, nz, tw, s);
+    case 1024: return launch_strided_n<T, 1024, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, z0, nz, tw, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <typename T, int N, int SIGN, int MODE>
-static hipError_t launch_contig_n(const void* in, void* out, int n0, int n1, int d0, int d1, int nc2,
-                                  const double* D0, const double* D1, const double* D2, const C<T>* tw,
+static hipError_t launch_contig_n(const void* in, void* out, int n0, int n1, int d0, int d1, int nc2, int z0,
+                                  int nz, const double* D0, const double* D1, const double* D2, const C<T>* tw,
                                   hipStream_t s) {
+  if (z0 < 0 || z0 >= N || nz < 0 || nz > N) return hipErrorInvalidValue;
   constexpr int TL = N / Radix<T, N, true>::R1;
   constexpr int LS = N + N / Radix<T, N, true>::R1;
   int B = 256 / TL;
@@ -372,33 +382,33 @@ static hipError_t launch_contig_n(const void* in, void* out, int n0, int n1, int
   const size_t shm = static_cast<size_t>(B) * LS * sizeof(LdsElem<T, N>);
   const int blocks = (nlines + B - 1) / B;
   hipLaunchKernelGGL((k_fft_contig<T, N, SIGN, MODE>), dim3(blocks), dim3(B * TL), shm, s, in, out, n0, n1, d0, d1,
-                     nc2, D0, D1, D2, tw, B, nlines);
+                     nc2, z0, nz, D0, D1, D2, tw, B, nlines);
   return hipGetLastError();
 }
 
 template <typename T, int SIGN, int MODE>
-hipError_t launch_contig(int n, const void* in, void* out, int n0, int n1, int d0, int d1, int nc2,
+hipError_t launch_contig(int n, const void* in, void* out, int n0, int n1, int d0, int d1, int nc2, int z0, int nz,
                                 const double* D0, const double* D1, const double* D2, const C<T>* tw,
                                 hipStream_t s) {
   switch (n) {
-    case 8: return launch_contig_n<T, 8, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, D0, D1, D2, tw, s);
-    case 16: return launch_contig_n<T, 16, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, D0, D1, D2, tw, s);
-    case 32: return launch_contig_n<T, 32, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, D0, D1, D2, tw, s);
-    case 64: return launch_contig_n<T, 64, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, D0, D1, D2, tw, s);
-    case 128: return launch_contig_n<T, 128, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, D0, D1, D2, tw, s);
-    case 256: return launch_contig_n<T, 256, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, D0, D1, D2, tw, s);
-    case 512: return launch_contig_n<T, 512, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, D0, D1, D2, tw, s);
-    case 1024: return launch_contig_n<T, 1024, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, D0, D1, D2, tw, s);
+    case 8: return launch_contig_n<T, 8, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s);
+    case 16: return launch_contig_n<T, 16, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s);
+    case 32: return launch_contig_n<T, 32, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s);
+    case 64: return launch_contig_n<T, 64, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s);
+    case 128: return launch_contig_n<T, 128, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s);
+    case 256: return launch_contig_n<T, 256, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s);
+    case 512: return launch_contig_n<T, 512, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s);
+    case 1024: return launch_contig_n<T, 1024, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 #define DDI_INST_STRIDED(T, S)                                                                                  \
-  template hipError_t launch_strided<T, S>(int, C<T>*, int, int, int, int, int, int, int, int, int, const C<T>*, \
-                                           hipStream_t);
+  template hipError_t launch_strided<T, S>(int, C<T>*, int, int, int, int, int, int, int, int, int, int, int,    \
+                                           const C<T>*, hipStream_t);
 #define DDI_INST_CONTIG(T, S, M)                                                                                \
-  template hipError_t launch_contig<T, S, M>(int, const void*, void*, int, int, int, int, int, const double*,   \
-                                             const double*, const double*, const C<T>*, hipStream_t);
+  template hipError_t launch_contig<T, S, M>(int, const void*, void*, int, int, int, int, int, int, int,        \
+                                             const double*, const double*, const double*, const C<T>*, hipStream_t);
 DDI_INST_STRIDED(double, 1)
 DDI_INST_STRIDED(double, -1)
 DDI_INST_STRIDED(float, 1)

@@ -747,18 +747,19 @@ static int64_t rows_bytes(const HostTables& H) {
 // Forward transform of the padded, deconvolved density onto the fine grid (pruned:
 // only lines that can hold non-zeros are transformed).
 template <typename T, int SIGN>
-static hipError_t type2_fft(DevicePlan& P, const T* rho, hipStream_t s, hipEvent_t* ev) {
+static hipError_t type2_fft(DevicePlan& P, int which, const T* rho, hipStream_t s, hipEvent_t* ev) {
   const HostTables& H = P.H;
+  const int z0 = H.sched[which].z0, nz = H.sched[which].nz;   // only the window is needed
   C<T>* F = reinterpret_cast<C<T>*>(P.fine);
   const C<T>* tw2 = reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[2])]);
-  DDI_CHECK((launch_contig<T, SIGN, R2C_PAD>(H.nf[2], rho, F, H.N[0], H.N[1], H.nf[0], H.nf[1], H.N[2],
+  DDI_CHECK((launch_contig<T, SIGN, R2C_PAD>(H.nf[2], rho, F, H.N[0], H.N[1], H.nf[0], H.nf[1], H.N[2], z0, nz,
                                              P.deconv[0], P.deconv[1], P.deconv[2], tw2, s)));
   DDI_REC(1);
-  DDI_CHECK((launch_strided<T, SIGN>(H.nf[1], F, 1, H.nf[0], H.nf[1], H.nf[2], H.N[0], 1, H.N[1], 1, 0,
+  DDI_CHECK((launch_strided<T, SIGN>(H.nf[1], F, 1, H.nf[0], H.nf[1], H.nf[2], H.N[0], 1, H.N[1], 1, 0, z0, nz,
                                      reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[1])]), s)));
   DDI_REC(2);
   if (H.nf[0] > 1) {
-    DDI_CHECK((launch_strided<T, SIGN>(H.nf[0], F, 0, H.nf[0], H.nf[1], H.nf[2], H.nf[1], 0, H.N[0], 1, 0,
+    DDI_CHECK((launch_strided<T, SIGN>(H.nf[0], F, 0, H.nf[0], H.nf[1], H.nf[2], H.nf[1], 0, H.N[0], 1, 0, z0, nz,
                                        reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[0])]), s)));
   }
   DDI_REC(3);
@@ -767,19 +768,20 @@ static hipError_t type2_fft(DevicePlan& P, const T* rho, hipStream_t s, hipEvent
 
 // Inverse transform of the spread grid, keeping only the modes of the compact grid.
 template <typename T, int SIGN>
-static hipError_t type1_fft(DevicePlan& P, T* phi, hipStream_t s, hipEvent_t* ev) {
+static hipError_t type1_fft(DevicePlan& P, int which, T* phi, hipStream_t s, hipEvent_t* ev) {
   const HostTables& H = P.H;
+  const int z0 = H.sched[which].z0, nz = H.sched[which].nz;   // the spread filled only the window
   C<T>* F = reinterpret_cast<C<T>*>(P.fine);
   if (H.nf[0] > 1) {
-    DDI_CHECK((launch_strided<T, SIGN>(H.nf[0], F, 0, H.nf[0], H.nf[1], H.nf[2], H.nf[1], 0, H.N[0], 0, 1,
+    DDI_CHECK((launch_strided<T, SIGN>(H.nf[0], F, 0, H.nf[0], H.nf[1], H.nf[2], H.nf[1], 0, H.N[0], 0, 1, z0, nz,
                                        reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[0])]), s)));
   }
   DDI_REC(7);
-  DDI_CHECK((launch_strided<T, SIGN>(H.nf[1], F, 1, H.nf[0], H.nf[1], H.nf[2], H.N[0], 1, H.N[1], 0, 1,
+  DDI_CHECK((launch_strided<T, SIGN>(H.nf[1], F, 1, H.nf[0], H.nf[1], H.nf[2], H.N[0], 1, H.N[1], 0, 1, z0, nz,
                                      reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[1])]), s)));
   DDI_REC(8);
   const C<T>* tw2 = reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[2])]);
-  DDI_CHECK((launch_contig<T, SIGN, C2R_TRUNC>(H.nf[2], F, phi, H.N[0], H.N[1], H.nf[0], H.nf[1], H.N[2],
+  DDI_CHECK((launch_contig<T, SIGN, C2R_TRUNC>(H.nf[2], F, phi, H.N[0], H.N[1], H.nf[0], H.nf[1], H.N[2], z0, nz,
                                                P.deconv[0], P.deconv[1], P.deconv[2], tw2, s)));
   DDI_REC(9);
   return hipSuccess;
@@ -925,8 +927,8 @@ template <typename T>
 hipError_t run_type2(DevicePlan& P, int which, const T* rho, Complex<T>* out, const double* scale,
                      double cscalar, int sign, hipStream_t s, hipEvent_t* ev) {
   DDI_REC(0);
-  if (sign < 0) DDI_CHECK((type2_fft<T, -1>(P, rho, s, ev)));
-  else DDI_CHECK((type2_fft<T, +1>(P, rho, s, ev)));
+  if (sign < 0) DDI_CHECK((type2_fft<T, -1>(P, which, rho, s, ev)));
+  else DDI_CHECK((type2_fft<T, +1>(P, which, rho, s, ev)));
   DDI_CHECK((interp<T>(P, which, out, scale, cscalar, s)));
   DDI_REC(4);
   return hipSuccess;
@@ -936,8 +938,8 @@ template <typename T>
 hipError_t run_type1(DevicePlan& P, int which, const Complex<T>* g, T* phi, int sign, hipStream_t s,
                      hipEvent_t* ev) {
   DDI_CHECK(spread<T>(P, which, g, s, ev));
-  if (sign > 0) return type1_fft<T, +1>(P, phi, s, ev);
-  return type1_fft<T, -1>(P, phi, s, ev);
+  if (sign > 0) return type1_fft<T, +1>(P, which, phi, s, ev);
+  return type1_fft<T, -1>(P, which, phi, s, ev);
 }
 
 // Forward (sign = +1: exp(-ikx) to the nodes, exp(+ikx) back) or literal adjoint (sign = -1)

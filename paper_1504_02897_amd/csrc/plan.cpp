@@ -172,6 +172,31 @@ std::string build_spread_schedule(const HostTables& t, const std::vector<int64_t
     }
     return cnt;
   };
+  // last-axis window: the complement of the longest circular run of kZAlign-blocks that no
+  // support touches (the whole axis when that run is empty or the axis is short)
+  {
+    const int n = t.nf[2];
+    S.z0 = 0;
+    S.nz = n;
+    if (n % kZAlign == 0 && n >= 4 * kZAlign) {
+      const int nb = n / kZAlign;
+      std::vector<char> hit(nb, 0);
+      for (int64_t s = 0; s < M; ++s) {
+        if (!used(s)) continue;
+        for (int i = 0; i < t.W[2]; ++i) hit[((t.l0[3 * s + 2] + i) % n) / kZAlign] = 1;
+      }
+      int best = 0, best_end = 0;
+      for (int i = 0, run = 0; i < 2 * nb; ++i) {   // twice round: runs that wrap
+        run = hit[i % nb] ? 0 : std::min(run + 1, nb);
+        if (run > best) { best = run; best_end = i % nb; }
+      }
+      if (best > 0 && best < nb) {
+        S.z0 = ((best_end + 1) % nb) * kZAlign;
+        S.nz = (nb - best) * kZAlign;
+      }
+    }
+  }
+  auto in_window = [&](int z) { return ((z - S.z0) % t.nf[2] + t.nf[2]) % t.nf[2] < S.nz; };
   std::vector<int64_t> count(ntile_total + 1, 0);
   int tx[kWMax], ty[kWMax], tz[kWMax];
   for (int pass = 0; pass < 2; ++pass) {
@@ -201,6 +226,10 @@ std::string build_spread_schedule(const HostTables& t, const std::vector<int64_t
   for (int64_t tord = 0; tord < ntile_total; ++tord) {
     const int64_t tid = tile_order[tord];
     int64_t beg = count[tid], n = count[tid + 1] - count[tid];
+    if (!in_window(static_cast<int>(tid % t.ntiles[2]) * t.tile[2])) {
+      if (n > 0) return "internal: a node support outside the last-axis window";
+      continue;                              // never read: no item
+    }
     if (n <= chunk) {
       S.items.push_back({static_cast<int32_t>(tid), static_cast<int32_t>(beg), static_cast<int32_t>(n), -1});
     } else {
