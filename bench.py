@@ -32,9 +32,10 @@ METRIC = "DDI evals/s at 128³ (FP64 vs mixed, rel L∞ ≤1e-6); fwd+adjoint ms
 def stage_model(plan, real_bytes, cplx_bytes):
     """Algorithmic HBM bytes and flops of each stage of one apply.
 
-    FFT passes: the active part of each line is read and written once.  Interpolation:
-    the fine grid is read once, plus node records and node values.  Spread: the fine grid
-    is written once, plus node records, node values and the tile lists.  Flops of
+    FFT passes: the active part of each line is read and written once, over the lines at
+    the last-axis positions the operator needs (the window of the kept half of the nodes).
+    Interpolation: the fine grid's window is read once, plus node records and node values.
+    Spread: the window is written once, plus node records, node values and the tile lists.  Flops of
     interpolation/spread: 4 per (node, grid point) pair (a real weight times a complex
     value accumulated), w^d pairs per node, over the nodes the operator visits (one per
     +-k pair); of an FFT pass: 5 n log2 n per line.
@@ -50,13 +51,14 @@ def stage_model(plan, real_bytes, cplx_bytes):
     def fftf(n, lines):
         return 5.0 * n * math.log2(n) * lines if n > 1 else 0.0
 
+    z = plan.info["apply_window"]    # last-axis positions of the fine grid the operator transforms
     st = {}
-    st["fft_last_pad"] = (N[0] * N[1] * N[2] * real_bytes + N[0] * N[1] * nf[2] * c, fftf(nf[2], N[0] * N[1]))
-    st["fft_axis1_t2"] = (N[0] * N[1] * nf[2] * c + N[0] * nf[1] * nf[2] * c, fftf(nf[1], N[0] * nf[2]))
-    st["fft_axis0_t2"] = ((N[0] * nf[1] * nf[2] * c + nf[0] * nf[1] * nf[2] * c) if nf[0] > 1 else 0,
-                          fftf(nf[0], nf[1] * nf[2]))
-    st["interp"] = (nf[0] * nf[1] * nf[2] * c + M * (rec + c + 8), 4.0 * M * w ** d)
-    st["spread"] = (nf[0] * nf[1] * nf[2] * c + M * (rec + c) + 4 * plan.info["spread_entries"], 4.0 * M * w ** d)
+    st["fft_last_pad"] = (N[0] * N[1] * N[2] * real_bytes + N[0] * N[1] * z * c, fftf(nf[2], N[0] * N[1]))
+    st["fft_axis1_t2"] = (N[0] * N[1] * z * c + N[0] * nf[1] * z * c, fftf(nf[1], N[0] * z))
+    st["fft_axis0_t2"] = ((N[0] * nf[1] * z * c + nf[0] * nf[1] * z * c) if nf[0] > 1 else 0,
+                          fftf(nf[0], nf[1] * z))
+    st["interp"] = (nf[0] * nf[1] * z * c + M * (rec + c + 8), 4.0 * M * w ** d)
+    st["spread"] = (nf[0] * nf[1] * z * c + M * (rec + c) + 4 * plan.info["spread_entries"], 4.0 * M * w ** d)
     st["spread_reduce"] = (0.0, 0.0)
     st["fft_axis0_t1"] = st["fft_axis0_t2"]
     st["fft_axis1_t1"] = st["fft_axis1_t2"]

@@ -257,6 +257,7 @@ ddi_status ddi_plan_info(ddi_plan_t plan, ddi_plan_info_t* info) {
   info->m_nominal = H.m_nominal;
   info->m_half = 0;
   for (double f : H.half_factor) info->m_half += f > 0.0 ? 1 : 0;
+  info->apply_window = H.sched[ddi::kHalf].nz;
   for (int a = 0; a < 3; ++a) info->n_fine[a] = H.nf[a];
   info->width = H.w;
   info->es_beta = H.es_beta;

@@ -43,6 +43,7 @@ class GPEParamsC(ctypes.Structure):
 
 class PlanInfo(ctypes.Structure):
     _fields_ = [("m_eff", ctypes.c_int64), ("m_nominal", ctypes.c_int64), ("m_half", ctypes.c_int64),
+                ("apply_window", ctypes.c_int64),
                 ("n_fine", ctypes.c_int64 * 3),
                 ("width", ctypes.c_int32), ("es_beta", ctypes.c_double), ("kmax", ctypes.c_double),
                 ("spread_items", ctypes.c_int64), ("spread_entries", ctypes.c_int64),
@@ -133,7 +134,7 @@ class DDIPlan:
         _check(_lib.ddi_plan(ctypes.byref(p), _stream(), ctypes.byref(self._h)))
         info = PlanInfo()
         _check(_lib.ddi_plan_info(self._h, ctypes.byref(info)))
-        self.info = {"m_eff": info.m_eff, "m_nominal": info.m_nominal, "m_half": info.m_half,
+        self.info = {"m_eff": info.m_eff, "m_nominal": info.m_nominal, "m_half": info.m_half, "apply_window": info.apply_window,
                      "n_fine": tuple(info.n_fine),
                      "width": info.width, "es_beta": info.es_beta, "kmax": info.kmax,
                      "spread_items": info.spread_items, "spread_entries": info.spread_entries,
