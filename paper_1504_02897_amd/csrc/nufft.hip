@@ -350,7 +350,7 @@ __device__ inline double row_load(__amdgpu_buffer_rsrc_t rows, unsigned off) {
 // current stage's products.  The tile goes through LDS and is written eight lanes per row
 // along the last axis (or to its partial slot, in k_spread's slot layout).
 template <typename T>
-__global__ void __launch_bounds__(64) k_spread_mfma(C<T>* __restrict__ F, C<T>* __restrict__ partial,
+__global__ void __launch_bounds__(64, 4) k_spread_mfma(C<T>* __restrict__ F, C<T>* __restrict__ partial,
                                                     const T* __restrict__ pads, const C<T>* __restrict__ g,
                                                     const int2* __restrict__ ent,
                                                     const SpreadItem* __restrict__ items, int nf1, int nf2, int nt1,
