@@ -114,7 +114,8 @@ typedef struct {
   int64_t m_half;       /* nodes interpolated and spread by ddi_apply: one per +-k pair */
   int64_t apply_window; /* positions along the fine grid's last axis that ddi_apply transforms:
                            the kept member of each pair lies on one side, so their supports
-                           cover a window of n_fine[2] (multiples of 16; n_fine[2] if none) */
+                           cover a window of n_fine[2] (a multiple of 8 in FP64, 16 in mixed;
+                           n_fine[2] if there is no gap) */
   int64_t n_fine[3];    /* oversampled FFT grid (n_fine[0] = 1 in 2D) */
   int32_t width;        /* kernel width w */
   double es_beta;       /* kernel shape parameter */

@@ -46,7 +46,6 @@ constexpr int kSpreadChunkMfma = DDI_SPREAD_CHUNK_MFMA;
 constexpr int kRowLen = kWMax;    // weight row of the matrix-core kernels: w weights, then zeros
 constexpr int kOffBias = 8;       // entry offsets are stored biased by this (non-negative bytes)
 constexpr int kEntPad = 32;       // zero entries after the last one (blocks of 16 may read past an item)
-constexpr int kZAlign = 16;       // granularity of the last-axis window of a schedule
 #ifndef DDI_INTERP_TILE
 #define DDI_INTERP_TILE 1
 #endif
@@ -118,7 +117,7 @@ struct Schedule {
   // is the tile origin minus the support origin on axis a; kEntPad zero entries follow
   std::vector<int32_t> ent;
   // Last-axis window: every fine position that a scheduled node's support touches lies in
-  // [z0, z0 + nz) (mod n_fine[2]); z0 and nz are multiples of kZAlign.  The FFT passes of
+  // [z0, z0 + nz) (mod n_fine[2]); z0 and nz are multiples of HostTables::zalign.  The FFT passes of
   // this schedule read and write only the window, and the spread writes only its tiles.
   int32_t z0 = 0;
   int32_t nz = 0;
@@ -161,6 +160,9 @@ struct HostTables {
   // positions are one contiguous run of its weight row (no periodic wrap inside a tile); and
   // the weight rows fit 32-bit byte offsets (2 GiB)
   bool row_windows = false;
+  // granularity of the schedules' last-axis windows: a multiple of kTileZ; 8 in FP64, 16 in FP32
+  // (the strided FFT passes cover a window in blocks of lines that divide it: 128-byte rows)
+  int zalign = 16;
   Schedule sched[2];
 };
 

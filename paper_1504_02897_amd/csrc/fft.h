@@ -16,7 +16,7 @@ enum ContigMode { R2C_PAD = 0, C2C = 1, C2R_TRUNC = 2 };
 // oversampled axis when o_compact); in_c / out_c: only the nc active positions
 // of each line are read / written (exp(SIGN 2 pi i jk/n)).  Only the lines at
 // last-axis positions [z0, z0 + nz) (mod d2) are transformed: z0 and nz are
-// multiples of kZAlign, or z0 = 0 and nz = d2.
+// multiples of 8, or z0 = 0 and nz = d2.
 template <typename T, int SIGN>
 hipError_t launch_strided(int n, Complex<T>* F, int axis, int d0, int d1, int d2, int n_o, int o_compact, int nc,
                           int in_c, int out_c, int z0, int nz, const Complex<T>* tw, hipStream_t s);

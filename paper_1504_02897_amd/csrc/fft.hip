@@ -332,13 +332,13 @@ static hipError_t launch_strided_n(C<T>* F, int axis, int d0, int d1, int d2, in
   constexpr int TL = N / Radix<T, N, false>::R1;
   // lines per workgroup: at least 256 threads, and row segments of >= 128 B along the
   // contiguous axis (coalescing) as far as 1024 threads and 64 KB of LDS allow; a window
-  // of the last axis is covered in blocks of at most kZAlign lines
+  // of the last axis is covered in blocks of lines that divide its start and length
   int B = 256 / TL;
   while (B * static_cast<int>(sizeof(C<T>)) < 128 && 2 * B * TL <= 1024 &&
          static_cast<size_t>(2 * B) * N * sizeof(LdsElem<T, N>) <= 65536)
     B *= 2;
-  if (nz < d2) B = std::min(B, kZAlign);
   while (B > d2) B >>= 1;
+  while (B > 1 && (z0 % B != 0 || nz % B != 0)) B >>= 1;
   if (z0 % B != 0 || nz % B != 0 || nz > d2 || z0 < 0 || z0 >= d2) return hipErrorInvalidValue;
   const size_t shm = static_cast<size_t>(B) * N * sizeof(LdsElem<T, N>);
   const int nzb = nz / B;

@@ -172,18 +172,18 @@ std::string build_spread_schedule(const HostTables& t, const std::vector<int64_t
     }
     return cnt;
   };
-  // last-axis window: the complement of the longest circular run of kZAlign-blocks that no
+  // last-axis window: the complement of the longest circular run of zalign-blocks that no
   // support touches (the whole axis when that run is empty or the axis is short)
   {
-    const int n = t.nf[2];
+    const int n = t.nf[2], za = t.zalign;
     S.z0 = 0;
     S.nz = n;
-    if (n % kZAlign == 0 && n >= 4 * kZAlign) {
-      const int nb = n / kZAlign;
+    if (n % za == 0 && n >= 4 * za) {
+      const int nb = n / za;
       std::vector<char> hit(nb, 0);
       for (int64_t s = 0; s < M; ++s) {
         if (!used(s)) continue;
-        for (int i = 0; i < t.W[2]; ++i) hit[((t.l0[3 * s + 2] + i) % n) / kZAlign] = 1;
+        for (int i = 0; i < t.W[2]; ++i) hit[((t.l0[3 * s + 2] + i) % n) / za] = 1;
       }
       int best = 0, best_end = 0;
       for (int i = 0, run = 0; i < 2 * nb; ++i) {   // twice round: runs that wrap
@@ -191,8 +191,8 @@ std::string build_spread_schedule(const HostTables& t, const std::vector<int64_t
         if (run > best) { best = run; best_end = i % nb; }
       }
       if (best > 0 && best < nb) {
-        S.z0 = ((best_end + 1) % nb) * kZAlign;
-        S.nz = (nb - best) * kZAlign;
+        S.z0 = ((best_end + 1) % nb) * za;
+        S.nz = (nb - best) * za;
       }
     }
   }
@@ -539,6 +539,7 @@ std::string build_tables(const ddi_params& p, HostTables& t, int* status) {
                      [&](int64_t x, int64_t y) { return tkey[x] < tkey[y]; });
   }
   // (the matrix-core kernels address the weight rows with 32-bit byte offsets)
+  t.zalign = p.prec == DDI_FP64 ? 8 : 16;
   t.row_windows = t.dim == 3 && (t.M + 1) * 3 * kRowLen * static_cast<int64_t>(sizeof(double)) < (int64_t(1) << 31);
   for (int a = 0; a < 3; ++a) t.row_windows = t.row_windows && t.tile[a] == 8 && t.nf[a] >= t.W[a] + 8;
   for (int which = 0; which < 2; ++which) {

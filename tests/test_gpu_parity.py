@@ -158,10 +158,11 @@ def test_anisotropic_grid_two_axes_fp64():
     assert err < FP64_TOL
     # the apply transforms a last-axis window of the fine grid: recompute it from the oracle's
     # quadrature (kept member of each +-k pair: the lower (polar, azimuthal) index) and the
-    # kernel supports, in blocks of 16 positions
+    # kernel supports, in blocks of 8 positions (FP64)
     quad, _ = O.ddi_nodes(prob)
     nf, w = plan.info["n_fine"][2], plan.info["width"]
-    nb, npol, nazi = nf // 16, prob.n_pol, prob.n_azi
+    za = 8
+    nb, npol, nazi = nf // za, prob.n_pol, prob.n_azi
     idx = {tuple(t) for t in quad.index.tolist()}
     hit = np.zeros(nb, bool)
     h = 2 * L[2] / n[2]
@@ -170,12 +171,12 @@ def test_anisotropic_grid_two_axes_fp64():
         if partner in idx and partner != (a, b, c) and partner < (a, b, c):
             continue
         l0 = math.ceil(kz * h * nf / (2 * math.pi) - w / 2)
-        hit[[((l0 + i) % nf) // 16 for i in range(w)]] = True
+        hit[[((l0 + i) % nf) // za for i in range(w)]] = True
     run = best = 0
     for i in range(2 * nb):
         run = 0 if hit[i % nb] else min(run + 1, nb)
         best = max(best, run)
-    assert plan.info["apply_window"] == nf - 16 * best < nf
+    assert plan.info["apply_window"] == nf - za * best < nf
 
 
 def test_adjoint_literal_and_dot_product_fp64():
