@@ -291,12 +291,14 @@ __global__ void __launch_bounds__(64) k_spread(C<T>* __restrict__ F, C<T>* __res
 }
 
 // Cooperative weight loads of the matrix-core kernels.  For a block of 16 (tile, node)
-// entries, load j (0..5) covers window w = 8 j + (lane >> 3) -- entry w / 3, axis w % 3 -- at
-// tile position t = lane & 7, so eight lanes read one contiguous run of a weight row.  The
-// entry records and weight rows are read as raw buffers: a lane offset (32-bit) plus the
-// block's uniform offset, with no per-lane 64-bit address arithmetic.  The entry table ends
-// with kEntPad zero records, so a block may run past its item's entries; positions outside
-// the node's weight row read the zero record at byte offset zrec of the rows.
+// entries, lane (g, t) = (lane / 8, lane % 8) takes the entries 2 g and 2 g + 1 (one 16-byte
+// load of their two records) and, for load j (0..5), the window of entry 2 g + j / 3 on axis
+// j % 3 at tile position t: eight lanes read one contiguous run of a weight row.  The entry
+// records and weight rows are read as raw buffers: a lane offset (32-bit) plus the block's
+// uniform offset, with no per-lane 64-bit address arithmetic.  The entry table ends with
+// kEntPad zero records, so a block may run past its item's entries; positions outside the
+// node's weight row read the zero record at byte offset zrec of the rows.  The loaded
+// weights are published to LDS as [entry][axis][8 tile positions].
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 constexpr int kBufferWord3 = 0x00020000;     // raw buffer descriptor word 3 (32-bit data, no swizzle)
 
@@ -306,30 +308,32 @@ __device__ inline __amdgpu_buffer_rsrc_t raw_buffer(const X* p, int64_t bytes) {
 }
 
 struct CoopLanes {
-  unsigned eo[6];                            // byte offset of the window's entry record in the block
-  int sh[6];                                 // 8 * axis: bit offset of the axis's packed window start
+  unsigned eo;                               // byte offset of the lane's two entry records in the block
   int tb;                                    // t - kOffBias
+  int slot;                                  // LDS slot of load 0 (entry 2 g, axis 0, position t)
   __device__ explicit CoopLanes(int lane) {
+    eo = static_cast<unsigned>(lane >> 3) * 2 * sizeof(int2);
     tb = (lane & 7) - kOffBias;
-#pragma unroll
-    for (int j = 0; j < 6; ++j) {
-      const int w = 8 * j + (lane >> 3);
-      eo[j] = static_cast<unsigned>(w / 3) * sizeof(int2);
-      sh[j] = 8 * (w % 3);
-    }
+    slot = (lane >> 3) * 48 + (lane & 7);
   }
-  // entry record of load j; blk = byte offset of the block's first record
-  __device__ int2 entry(__amdgpu_buffer_rsrc_t ent, int blk, int j) const {
-    return __builtin_bit_cast(int2, __builtin_amdgcn_raw_buffer_load_b64(ent, eo[j], blk, 0));
+  // the lane's two entry records; blk = byte offset of the block's first record
+  __device__ void entries(__amdgpu_buffer_rsrc_t ent, int blk, int2* en) const {
+    const int4 v = __builtin_bit_cast(int4, __builtin_amdgcn_raw_buffer_load_b128(ent, eo, blk, 0));
+    en[0] = make_int2(v.x, v.y);
+    en[1] = make_int2(v.z, v.w);
   }
-  // byte offset in the weight rows of load j's position for entry record en
+  // byte offset in the weight rows of load j's position, en = the lane's two entry records
   template <typename T>
-  __device__ unsigned row_offset(int2 en, int j, unsigned zrec) const {
-    const int d = ((en.y >> sh[j]) & 255) + tb;  // support index of this tile position
-    const unsigned at = __umul24(static_cast<unsigned>(en.x), 3 * kRowLen) + static_cast<unsigned>(d + 2 * sh[j]);
+  __device__ unsigned row_offset(const int2* en, int j, unsigned zrec) const {
+    const int2 e = en[j / 3];
+    const int a = j % 3;
+    const int d = ((e.y >> (8 * a)) & 255) + tb;  // support index of this tile position
+    const unsigned at = __umul24(static_cast<unsigned>(e.x), 3 * kRowLen) + static_cast<unsigned>(a * kRowLen + d);
     const unsigned off = at * static_cast<unsigned>(sizeof(T));
     return static_cast<unsigned>(d) < static_cast<unsigned>(kRowLen) ? off : zrec;
   }
+  // LDS index of load j's value in the [entry][axis][8] weight buffer
+  __device__ int wslot(int j) const { return slot + (j / 3) * 24 + (j % 3) * 8; }
 };
 
 template <typename T>
@@ -386,19 +390,18 @@ __global__ void __launch_bounds__(64, 4) k_spread_mfma(C<T>* __restrict__ F, C<T
   const unsigned go = static_cast<unsigned>(lane >> 1) * sizeof(int2);
   auto load_stage = [&](int st, double* raw, double& graw) {
     const int blk = (it.start + 16 * st) * static_cast<int>(sizeof(int2));
-    int2 en[6];
-#pragma unroll
-    for (int j = 0; j < 6; ++j) en[j] = cl.entry(ent_r, blk, j);
+    int2 en[2];
+    cl.entries(ent_r, blk, en);
     const int2 eg = __builtin_bit_cast(int2, __builtin_amdgcn_raw_buffer_load_b64(ent_r, go, blk, 0));
 #pragma unroll
-    for (int j = 0; j < 6; ++j) raw[j] = row_load<T>(rows_r, cl.row_offset<T>(en[j], j, zrec));
+    for (int j = 0; j < 6; ++j) raw[j] = row_load<T>(rows_r, cl.row_offset<T>(en, j, zrec));
     const bool valid = lane < 32 && 16 * st + (lane >> 1) < it.count;
     const C<T> gq = g[eg.x];
     graw = valid ? static_cast<double>((lane & 1) ? gq.im : gq.re) : 0.0;
   };
   auto publish = [&](const double* raw, double graw) {
 #pragma unroll
-    for (int j = 0; j < 6; ++j) wts[64 * j + lane] = raw[j];
+    for (int j = 0; j < 6; ++j) wts[cl.wslot(j)] = raw[j];
     if (lane < 32) gv[lane] = graw;
   };
   double raw[6], graw = 0.0;
@@ -571,15 +574,12 @@ __global__ void __launch_bounds__(64) k_interp_mfma(const C<T>* __restrict__ F, 
   // loads are pipelined across blocks: entry records two blocks ahead, weight rows one ahead.
   const CoopLanes cl(lane);
   const __amdgpu_buffer_rsrc_t ent_r = raw_buffer(ent, ent_bytes), rows_r = raw_buffer(pads, rows_bytes);
-  auto load_ent = [&](int mb, int2* en) {
-#pragma unroll
-    for (int j = 0; j < 6; ++j) en[j] = cl.entry(ent_r, (it.start + 16 * mb) * static_cast<int>(sizeof(int2)), j);
-  };
+  auto load_ent = [&](int mb, int2* en) { cl.entries(ent_r, (it.start + 16 * mb) * static_cast<int>(sizeof(int2)), en); };
   auto load_rows = [&](const int2* en, double* raw) {
 #pragma unroll
-    for (int j = 0; j < 6; ++j) raw[j] = row_load<T>(rows_r, cl.row_offset<T>(en[j], j, zrec));
+    for (int j = 0; j < 6; ++j) raw[j] = row_load<T>(rows_r, cl.row_offset<T>(en, j, zrec));
   };
-  int2 en_a[6], en_b[6];
+  int2 en_a[2], en_b[2];
   double raw[6];
   load_ent(0, en_a);
   if (nmb > 1) load_ent(1, en_b);
@@ -598,7 +598,7 @@ __global__ void __launch_bounds__(64) k_interp_mfma(const C<T>* __restrict__ F, 
   }
   load_rows(en_a, raw);
 #pragma unroll
-  for (int j = 0; j < 6; ++j) wts[64 * j + lane] = raw[j];
+  for (int j = 0; j < 6; ++j) wts[cl.wslot(j)] = raw[j];
   __syncthreads();
   const int kk = lane >> 4, col = lane & 15, xo = col >> 1;
   const int yo = 4 * (kk >> 1), zo = 4 * (kk & 1);
@@ -616,7 +616,7 @@ __global__ void __launch_bounds__(64) k_interp_mfma(const C<T>* __restrict__ F, 
     if (more) {
       load_rows(en_b, raw);
 #pragma unroll
-      for (int j = 0; j < 6; ++j) en_a[j] = en_b[j];
+      for (int j = 0; j < 2; ++j) en_a[j] = en_b[j];
       if (mb + 2 < nmb) load_ent(mb + 2, en_b);
     }
     dbl4 acc = {0.0, 0.0, 0.0, 0.0};
@@ -651,7 +651,7 @@ __global__ void __launch_bounds__(64) k_interp_mfma(const C<T>* __restrict__ F, 
     if (more) {
       __syncthreads();                       // every lane has read this block's weights
 #pragma unroll
-      for (int j = 0; j < 6; ++j) wts[64 * j + lane] = raw[j];
+      for (int j = 0; j < 6; ++j) wts[cl.wslot(j)] = raw[j];
       __syncthreads();
     }
   }
