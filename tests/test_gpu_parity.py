@@ -56,6 +56,30 @@ def oracle_rows(plan, prob):
     return rows, quad, c
 
 
+def expected_window(plan, prob, za):
+    """Last-axis window of the operator recomputed from the oracle's quadrature: the kept member
+    of each +-k pair (the lower (polar, azimuthal) index), its kernel support on the last axis,
+    and the complement of the longest circular run of untouched blocks of za positions."""
+    quad, _ = O.ddi_nodes(prob)
+    nf, w = plan.info["n_fine"][2], plan.info["width"]
+    nb, npol, nazi = nf // za, prob.n_pol, prob.n_azi
+    last = prob.dim - 1                    # the paper's z (3D) or y (2D)
+    h = 2 * prob.L[last] / prob.n[last]
+    idx = {tuple(t) for t in quad.index.tolist()}
+    hit = np.zeros(nb, bool)
+    for (a, b, c), kl in zip(quad.index.tolist(), quad.k[:, last]):
+        partner = (a, npol - 1 - b if prob.dim == 3 else 0, (c + nazi // 2) % nazi)
+        if partner in idx and partner != (a, b, c) and partner < (a, b, c):
+            continue
+        l0 = math.ceil(kl * h * nf / (2 * math.pi) - w / 2)
+        hit[[((l0 + i) % nf) // za for i in range(w)]] = True
+    run = best = 0
+    for i in range(2 * nb):
+        run = 0 if hit[i % nb] else min(run + 1, nb)
+        best = max(best, run)
+    return nf - za * best
+
+
 # ---------------------------------------------------------------- plan tables
 def test_plan_nodes_match_oracle_quadrature():
     say("case: plan nodes 32^3 / 32x16x32")
@@ -156,27 +180,7 @@ def test_anisotropic_grid_two_axes_fp64():
     err = relinf(phi, ref)
     say(f"  rel Linf = {err:.3e}")
     assert err < FP64_TOL
-    # the apply transforms a last-axis window of the fine grid: recompute it from the oracle's
-    # quadrature (kept member of each +-k pair: the lower (polar, azimuthal) index) and the
-    # kernel supports, in blocks of 8 positions (FP64)
-    quad, _ = O.ddi_nodes(prob)
-    nf, w = plan.info["n_fine"][2], plan.info["width"]
-    za = 8
-    nb, npol, nazi = nf // za, prob.n_pol, prob.n_azi
-    idx = {tuple(t) for t in quad.index.tolist()}
-    hit = np.zeros(nb, bool)
-    h = 2 * L[2] / n[2]
-    for (a, b, c), kz in zip(quad.index.tolist(), quad.k[:, 2]):
-        partner = (a, npol - 1 - b, (c + nazi // 2) % nazi)
-        if partner in idx and partner != (a, b, c) and partner < (a, b, c):
-            continue
-        l0 = math.ceil(kz * h * nf / (2 * math.pi) - w / 2)
-        hit[[((l0 + i) % nf) // za for i in range(w)]] = True
-    run = best = 0
-    for i in range(2 * nb):
-        run = 0 if hit[i % nb] else min(run + 1, nb)
-        best = max(best, run)
-    assert plan.info["apply_window"] == nf - za * best < nf
+    assert plan.info["apply_window"] == expected_window(plan, prob, 8) < plan.info["n_fine"][2]
 
 
 def test_adjoint_literal_and_dot_product_fp64():
@@ -233,6 +237,7 @@ def test_2d_mixture_with_noise_fp64():
     say("case: 2D 128^2 mixture + noise")
     n, L = (128, 128), (8.0, 8.0)
     plan, prob = make(2, n, L, (64, 1, 128), dip_n=(math.sqrt(0.5), 0.0, math.sqrt(0.5)))
+    assert plan.info["apply_window"] == expected_window(plan, prob, 8) < plan.info["n_fine"][2]
     lumps, rng = I.mixture_lumps(2, 2, (1, 6))
     psi = I.lumps_on_grid(lumps, n, L)
     psi = psi + 0.1 * np.max(np.abs(psi)) * rng.uniform(0, 1, n) * np.exp(1j * rng.uniform(0, 2 * np.pi, n))
@@ -262,6 +267,7 @@ def test_mixture_64_mixed_precision():
     say("case: 64^3 mixture mixed")
     n, L = (64, 64, 64), (10.0,) * 3
     plan, prob = make(3, n, L, (48, 24, 48), dip_n=(0.3, 0.4, math.sqrt(0.75)), prec="mixed")
+    assert plan.info["apply_window"] == expected_window(plan, prob, 16) < plan.info["n_fine"][2]
     lumps, _ = I.mixture_lumps(5, 3, (1, 4))
     psi, _ = I.normalise(I.lumps_on_grid(lumps, n, L), n, L)
     rho32 = (np.abs(psi) ** 2).astype(np.float32)
