@@ -3,16 +3,19 @@
 //   type-2 (grid -> nodes): deconvolve + zero-pad fused into the first FFT pass, pruned
 //     3-pass FFT on the oversampled grid, then interpolation at the quadrature nodes with the
 //     weights g_q = c_q prod(h) rhohat_q applied at the end.  FP64 interpolation in 3D is
-//     tile-owned: a wave stages one 8 x 8 x 8 tile of the fine grid in LDS, its lanes are the
-//     (tile, node) entries of that tile, and one partial per entry is summed per node by a
-//     gather kernel (the fine grid is read once).  Otherwise interpolation is node-owned: nodes
-//     grouped by home block read an LDS-staged support region, the rest read the grid
-//     directly (one wave per four nodes, compile-time kernel width).
-//   type-1 (nodes -> grid): tile-owned spread (a wave owns an 8 x 8 x 8 block of the fine
-//     grid in registers and sums the nodes whose support meets it, staged 64 at a time in LDS
-//     as tile-relative weight vectors; no atomics), hot tiles split into chunks whose partial
-//     tiles are summed in a fixed order by a reduce kernel; pruned 3-pass FFT with truncation,
-//     deconvolution and real part fused into the last pass.
+//     tile-owned: per 8 x 8 x 8 tile of the fine grid, the (tile, node) entries of the tile are
+//     contracted with the tile as FP64 matrix products (k_interp_mfma), one partial per entry,
+//     summed per node by a gather kernel (the fine grid is read once).  Otherwise interpolation
+//     is node-owned: nodes grouped by home block read an LDS-staged support region, the rest
+//     read the grid directly (one wave per four nodes, compile-time kernel width).
+//   type-1 (nodes -> grid): tile-owned spread, no atomics.  In 3D a tile is accumulated in
+//     registers by FP64 matrix products over its entries (k_spread_mfma); in 2D a wave owns a
+//     tile and sums the nodes staged 64 at a time in LDS as tile-relative weight vectors.  Hot
+//     tiles are split into chunks whose partial tiles a reduce kernel sums in a fixed order.
+//     Then a pruned 3-pass FFT with truncation, deconvolution and real part fused into the
+//     last pass.
+//   The operator (one node per +-k pair, all on one side of the last axis) transforms and
+//   spreads only the last-axis window that the kept nodes' supports cover.
 // Kernel weights are tabulated per node at plan time: nothing transcendental runs per apply.
 #include <hip/hip_runtime.h>
 
