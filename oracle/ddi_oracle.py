@@ -412,6 +412,32 @@ def gf_step(phi_n: np.ndarray, prob: DDIProblem, gp: GPEParams, dt: float, n_inn
     return phi1 / norm
 
 
+def ts_step(psi_n: np.ndarray, prob: DDIProblem, gp: GPEParams, dt: float, delta: float = 0.0):
+    """One step of the second-order time splitting of Eq. tssp2 for the dipolar GPE of
+    Eq. DipGPE1 with the cubic nonlinearity (sigma = 1), a time-independent dipole axis and the
+    damping f = delta >= 0 (Case I: delta = 0; Case II: linear damping delta > 0):
+
+        psi1      = IDFT[ exp(-i dt |mu_p|^2 / 4) DFT(psi_n) ]
+        psi2      = psi1 exp(-i [dt V + H + G]) exp(-F),   rho1 = |psi1|^2,
+                    H = beta s rho1,  G = lam s (A rho1),  F = delta dt,
+                    s = dt (delta = 0) or (1 - exp(-2 delta dt)) / (2 delta)
+        psi^{n+1} = IDFT[ exp(-i dt |mu_p|^2 / 4) DFT(psi2) ]
+
+    (H, G, F are the Case I / Case II closed forms of Eqs. fun1-fun2 with h(phi, s) =
+    phi exp(-2 delta s).)  The DFT is numpy's FFT (a library step); A is ddi_apply.
+    """
+    psi = np.asarray(psi_n, dtype=np.complex128)
+    kin = np.exp(-0.25j * dt * fourier_mu2(prob))
+    psi1 = np.fft.ifftn(kin * np.fft.fftn(psi))
+    rho1 = psi1.real ** 2 + psi1.imag ** 2
+    s = dt if delta == 0.0 else -math.expm1(-2.0 * delta * dt) / (2.0 * delta)
+    theta = dt * trap_potential(prob, gp) + gp.beta * s * rho1
+    if gp.lam != 0.0:
+        theta = theta + gp.lam * s * ddi_apply(rho1, prob)
+    psi2 = psi1 * np.exp(-1j * theta) * math.exp(-delta * dt)
+    return np.fft.ifftn(kin * np.fft.fftn(psi2))
+
+
 # --------------------------------------------------------------------------
 # Error metrics (Eq. error_l2 and the relative max-norm)
 # --------------------------------------------------------------------------

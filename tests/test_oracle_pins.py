@@ -383,3 +383,115 @@ def test_gradient_flow_energy_decreases_with_dipoles():
         Es.append(O.gpe_energy_grad(psi, p, gp, grad=False)[0][4])
         psi = O.gf_step(psi, p, gp, dt=0.05, n_inner=1)
     assert all(b <= a + 1e-12 for a, b in zip(Es, Es[1:]))
+
+
+# ---------------------------------------------------------------- time splitting (Eq. tssp2)
+def _mass(psi, p):
+    return p.cell * float(np.sum(np.abs(psi) ** 2))
+
+
+def _ts_case():
+    n, L = (16, 16, 16), (6.0,) * 3
+    p = O.DDIProblem(dim=3, n=n, L=L, dip_n=(0.6, 0.0, 0.8), n_rad=12, n_pol=6, n_azi=12)
+    gp = O.GPEParams(beta=20.0, lam=15.0, gamma=(1.0, 1.0, 2.0))
+    # a moving, asymmetric state: the trap Gaussian times a plane-wave phase, off centre
+    X = np.meshgrid(*p.axes(), indexing="ij")
+    psi = I.gf_initial(n, L, (1.0, 1.0, 2.0)) * np.exp(1j * (0.7 * X[0] - 0.4 * X[2])) \
+        * (1.0 + 0.3 * np.tanh(X[1]))
+    return p, gp, I.normalise(psi, n, L)[0]
+
+
+def test_time_splitting_free_gaussian_is_exact():
+    """beta = lam = 0, V = 0: the two half kinetic steps are the exact spectral propagator, and a
+    Gaussian exp(-|x|^2/2) becomes (1 + i t)^(-d/2) exp(-|x|^2 / (2 (1 + i t))) (free Schroedinger)."""
+    n, L = (64, 64), (8.0, 8.0)
+    p = O.DDIProblem(dim=2, n=n, L=L, n_rad=4, n_azi=4)
+    gp = O.GPEParams(V=np.zeros(n))
+    X = np.meshgrid(*p.axes(), indexing="ij")
+    r2 = X[0] ** 2 + X[1] ** 2
+    t = 0.5
+    psi = O.ts_step(np.exp(-0.5 * r2).astype(complex), p, gp, dt=t)
+    exact = np.exp(-r2 / (2.0 * (1.0 + 1j * t))) / (1.0 + 1j * t)
+    assert np.max(np.abs(psi - exact)) < 1e-10
+
+
+def test_time_splitting_is_second_order_on_the_ground_state():
+    """beta = lam = 0: the discrete ground state (dense eigensolve, energy e_g) evolves exactly as
+    exp(-i e_g t) phi_g; the splitting error at fixed t falls fourfold when dt halves."""
+    n, L, gamma = (16, 16, 16), (6.0,) * 3, (1.0, 1.5, 2.0)
+    phi_g, e_g = _discrete_harmonic_ground_state(n, L, gamma)
+    p = O.DDIProblem(dim=3, n=n, L=L, n_rad=4, n_pol=2, n_azi=4)
+    gp = O.GPEParams(gamma=gamma)
+    t = 0.2
+    errs = []
+    for steps in (10, 20):
+        psi = phi_g
+        for _ in range(steps):
+            psi = O.ts_step(psi, p, gp, dt=t / steps)
+        errs.append(np.max(np.abs(psi - np.exp(-1j * e_g * t) * phi_g)) / np.max(np.abs(phi_g)))
+    assert errs[0] < 1e-2
+    assert 3.5 < errs[0] / errs[1] < 4.5
+
+
+def test_time_splitting_mass_and_linear_damping():
+    """Case I conserves the mass; Case II (f = delta) multiplies it by exp(-2 delta dt)."""
+    p, gp, psi = _ts_case()
+    m0 = _mass(psi, p)
+    assert abs(_mass(O.ts_step(psi, p, gp, dt=0.01), p) - m0) < 1e-13 * m0
+    delta, dt = 0.7, 0.01
+    damped = O.ts_step(psi, p, gp, dt=dt, delta=delta)
+    assert abs(_mass(damped, p) - m0 * math.exp(-2 * delta * dt)) < 1e-13 * m0
+
+
+def test_time_splitting_is_time_reversible():
+    """The step is a symmetric composition and its nonlinear part keeps |psi|, so a step of
+    -dt undoes a step of dt."""
+    p, gp, psi = _ts_case()
+    back = O.ts_step(O.ts_step(psi, p, gp, dt=0.02), p, gp, dt=-0.02)
+    assert np.max(np.abs(back - psi)) < 1e-12 * np.max(np.abs(psi))
+
+
+def test_time_splitting_conserves_the_energy_to_second_order():
+    """With interaction and dipoles the energy of Eq. energy (the oracle's, pinned above) is
+    conserved up to the O(dt^2) splitting error: over the same time its largest deviation
+    falls about fourfold when dt halves (a wrong sign of any potential term gives an O(t) drift
+    that does not fall)."""
+    p, gp, psi0 = _ts_case()
+    E0 = O.gpe_energy_grad(psi0, p, gp, grad=False)[0][4]
+    dev = []
+    for steps in (4, 8):
+        psi, worst = psi0, 0.0
+        for _ in range(steps):
+            psi = O.ts_step(psi, p, gp, dt=0.02 / steps)
+            worst = max(worst, abs(O.gpe_energy_grad(psi, p, gp, grad=False)[0][4] - E0))
+        dev.append(worst / abs(E0))
+    assert dev[0] < 1e-4
+    assert 3.0 < dev[0] / dev[1] < 5.0
+
+
+@pytest.mark.parametrize("delta", [0.0, 0.7])
+def test_time_splitting_nonlinear_part_matches_ode_integration(delta):
+    """The closed forms of H, G, F (Case I and II) against a fine RK4 integration of the
+    nonlinear sub-problem (Eq. 2stepA) i psi_t = (V + beta |psi|^2 + lam A|psi|^2 - i delta) psi,
+    placed between the two exact half kinetic steps."""
+    p, gp, psi = _ts_case()
+    dt = 0.05
+    kin = np.exp(-0.25j * dt * O.fourier_mu2(p))
+    V = O.trap_potential(p, gp)
+
+    def rhs(y):
+        r = np.abs(y) ** 2
+        return (-1j * (V + gp.beta * r + gp.lam * O.ddi_apply(r, p)) - delta) * y
+
+    y = np.fft.ifftn(kin * np.fft.fftn(psi))
+    m = 100
+    h = dt / m
+    for _ in range(m):
+        k1 = rhs(y)
+        k2 = rhs(y + 0.5 * h * k1)
+        k3 = rhs(y + 0.5 * h * k2)
+        k4 = rhs(y + h * k3)
+        y = y + h / 6.0 * (k1 + 2 * k2 + 2 * k3 + k4)
+    ref = np.fft.ifftn(kin * np.fft.fftn(y))
+    got = O.ts_step(psi, p, gp, dt=dt, delta=delta)
+    assert np.max(np.abs(got - ref)) < 1e-9 * np.max(np.abs(ref))
