@@ -173,6 +173,21 @@ ddi_status gpe_gf_step(ddi_plan_t plan, const gpe_params* gp, double dt, int32_t
                        const void* psi_in_dev, void* psi_out_dev, void* stream);
 
 /*
+ * One step of the second-order time splitting for the dipolar GPE dynamics (Sec. 4.1,
+ * Eq. tssp2; the equation is Eq. DipGPE1 with the cubic nonlinearity and a time-independent
+ * dipole axis), damping f = delta >= 0 (Case I: delta = 0; Case II, linear damping: delta > 0):
+ *   psi1     = IDFT[exp(-i dt |mu|^2/4) DFT(psi_in)]
+ *   psi2     = psi1 exp(-i [dt V + s (beta |psi1|^2 + lambda Phi)]) exp(-delta dt),  Phi = A |psi1|^2,
+ *              s = dt (delta = 0) or (1 - exp(-2 delta dt)) / (2 delta)
+ *   psi_out  = IDFT[exp(-i dt |mu|^2/4) DFT(psi2)]
+ * with mu_p = pi p / L_i, p in [-N_i/2, N_i/2).  psi_in, psi_out: complex grids (may be the same
+ * buffer).  dt may be negative (a step back in time); delta must be >= 0.  The first GPE call on
+ * a plan allocates the GPE workspace.  Does not synchronise.
+ */
+ddi_status gpe_ts_step(ddi_plan_t plan, const gpe_params* gp, double dt, double delta,
+                       const void* psi_in_dev, void* psi_out_dev, void* stream);
+
+/*
  * Per-kernel timing of ddi_apply (sign = +1) or ddi_apply_adjoint (sign = -1):
  * runs the operator `reps` times on `stream` with HIP events between its
  * kernels and writes the mean duration in milliseconds of each stage to

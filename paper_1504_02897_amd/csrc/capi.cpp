@@ -407,4 +407,24 @@ ddi_status gpe_gf_step(ddi_plan_t plan, const gpe_params* gp, double dt, int32_t
   return DDI_OK;
 }
 
+ddi_status gpe_ts_step(ddi_plan_t plan, const gpe_params* gp, double dt, double delta, const void* psi_in_dev,
+                       void* psi_out_dev, void* stream) {
+  ddi_status st = check_plan(plan);
+  if (st != DDI_OK) return st;
+  if (!gp || !psi_in_dev || !psi_out_dev) return fail(DDI_EINVAL, "NULL argument");
+  if (dt == 0.0 || !std::isfinite(dt)) return fail(DDI_EINVAL, "dt must be finite and non-zero");
+  if (!(delta >= 0.0) || !std::isfinite(delta)) return fail(DDI_EINVAL, "delta must be finite and >= 0");
+  ddi::DevicePlan& P = plan->P;
+  st = P.mixed ? ensure_gpe<float>(P) : ensure_gpe<double>(P);
+  if (st != DDI_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = P.mixed ? ddi::run_ts_step<float>(P, *gp, dt, delta, static_cast<const ddi::Complex<float>*>(psi_in_dev),
+                                                   static_cast<ddi::Complex<float>*>(psi_out_dev), s)
+                         : ddi::run_ts_step<double>(P, *gp, dt, delta,
+                                                    static_cast<const ddi::Complex<double>*>(psi_in_dev),
+                                                    static_cast<ddi::Complex<double>*>(psi_out_dev), s);
+  if (e != hipSuccess) return hip_fail(e, "gpe_ts_step launch");
+  return DDI_OK;
+}
+
 }  // extern "C"

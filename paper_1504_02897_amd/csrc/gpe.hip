@@ -1,9 +1,11 @@
 // GPE kernels (Sec. 1, Eq. energy; Sec. 3.2 energy split; Sec. 3.1 gradient flow):
 // density, spectral kinetic energy and Laplacian through the batched FFT passes,
 // energy sums with FP64 block reductions (fixed order, deterministic), the
-// gradient dE/dconj(psi), and the stabilised backward-Euler Fourier step.
+// gradient dE/dconj(psi), the stabilised backward-Euler Fourier step, and the time-splitting
+// step of the dynamics (Sec. 4.1, Eq. tssp2).
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 
 #include "fft.h"
@@ -257,6 +259,40 @@ __global__ void __launch_bounds__(256) k_normalise(C<T>* __restrict__ x, int64_t
   }
 }
 
+// Time splitting (Eq. tssp2): x <- x exp(-i dt |mu|^2 / 4) / prod(N), in Fourier space (the
+// 1/prod(N) of the inverse FFT folded in)
+template <typename T>
+__global__ void __launch_bounds__(256) k_ts_kinetic(C<T>* __restrict__ x, int64_t n, GridGeo G, double qdt,
+                                                    double inv_ntot) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    double sn, cs;
+    sincos(qdt * mu2_of(i, G), &sn, &cs);    // exp(-i a) = cos a - i sin a
+    const C<T> v = x[i];
+    const double re = static_cast<double>(v.re), im = static_cast<double>(v.im);
+    x[i] = C<T>{static_cast<T>((re * cs + im * sn) * inv_ntot), static_cast<T>((im * cs - re * sn) * inv_ntot)};
+  }
+}
+
+// Time splitting, nonlinear sub-step (Eq. tssp2, Cases I/II): x <- x exp(-i [dt V + s (beta rho +
+// lam Phi)]) * damp, with rho = |x|^2 and Phi = A rho taken before the step
+template <typename T>
+__global__ void __launch_bounds__(256) k_ts_potential(C<T>* __restrict__ x, const T* __restrict__ rho,
+                                                      const T* __restrict__ phi, const T* __restrict__ Vext,
+                                                      int64_t n, GridGeo G, double dt, double sfac, double beta,
+                                                      double lam, double damp) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const double th = dt * trap_v(i, G, Vext) +
+                      sfac * (beta * static_cast<double>(rho[i]) + lam * static_cast<double>(phi[i]));
+    double sn, cs;
+    sincos(th, &sn, &cs);
+    const C<T> v = x[i];
+    const double re = static_cast<double>(v.re), im = static_cast<double>(v.im);
+    x[i] = C<T>{static_cast<T>((re * cs + im * sn) * damp), static_cast<T>((im * cs - re * sn) * damp)};
+  }
+}
+
 static GridGeo geo_of(const HostTables& H, const gpe_params& gp) {
   GridGeo G;
   G.N0 = H.N[0]; G.N1 = H.N[1]; G.N2 = H.N[2];
@@ -386,6 +422,41 @@ hipError_t run_gf_step(DevicePlan& P, const gpe_params& gp, double dt, int n_inn
 }
 
 
+// One step of the second-order time splitting (Eq. tssp2), cubic nonlinearity, time-independent
+// dipole axis, damping f = delta >= 0 (Case I: 0; Case II: linear): half kinetic step, the
+// nonlinear step with rho and Phi = A rho of the half-stepped state, half kinetic step.
+template <typename T>
+hipError_t run_ts_step(DevicePlan& P, const gpe_params& gp, double dt, double delta, const Complex<T>* psi_in,
+                       Complex<T>* psi_out, hipStream_t s) {
+  const HostTables& H = P.H;
+  const int64_t n = static_cast<int64_t>(H.N[0]) * H.N[1] * H.N[2];
+  const GridGeo G = geo_of(H, gp);
+  const double inv_ntot = 1.0 / static_cast<double>(n);
+  T* rho = reinterpret_cast<T*>(P.gpe_rho);
+  T* phi = reinterpret_cast<T*>(P.gpe_phi);
+  const T* Vext = reinterpret_cast<const T*>(gp.V_dev);
+  // Case II time factor (1 - exp(-2 delta dt)) / (2 delta), dt in Case I
+  const double sfac = delta == 0.0 ? dt : -std::expm1(-2.0 * delta * dt) / (2.0 * delta);
+  if (psi_out != psi_in) {
+    hipLaunchKernelGGL((k_copy<T>), dim3(ew_blocks(n)), dim3(256), 0, s, psi_in, psi_out, n);
+    DDI_CHECK(hipGetLastError());
+  }
+  auto half_kinetic = [&]() -> hipError_t {
+    DDI_CHECK((fft3_full<T, -1>(P, psi_out, s)));
+    hipLaunchKernelGGL((k_ts_kinetic<T>), dim3(ew_blocks(n)), dim3(256), 0, s, psi_out, n, G, 0.25 * dt, inv_ntot);
+    DDI_CHECK(hipGetLastError());
+    return fft3_full<T, +1>(P, psi_out, s);
+  };
+  DDI_CHECK(half_kinetic());
+  hipLaunchKernelGGL((k_density<T>), dim3(ew_blocks(n)), dim3(256), 0, s, psi_out, rho, n);
+  DDI_CHECK(hipGetLastError());
+  if (gp.lambda != 0.0) DDI_CHECK(run_apply<T>(P, rho, phi, +1, s, nullptr));
+  hipLaunchKernelGGL((k_ts_potential<T>), dim3(ew_blocks(n)), dim3(256), 0, s, psi_out, rho,
+                     gp.lambda != 0.0 ? phi : rho, Vext, n, G, dt, sfac, gp.beta, gp.lambda, std::exp(-delta * dt));
+  DDI_CHECK(hipGetLastError());
+  return half_kinetic();
+}
+
 template hipError_t run_gpe_energy_grad<double>(DevicePlan&, const gpe_params&, const Complex<double>*, double*,
                                                 Complex<double>*, hipStream_t);
 template hipError_t run_gpe_energy_grad<float>(DevicePlan&, const gpe_params&, const Complex<float>*, double*,
@@ -393,6 +464,10 @@ template hipError_t run_gpe_energy_grad<float>(DevicePlan&, const gpe_params&, c
 template hipError_t run_gf_step<double>(DevicePlan&, const gpe_params&, double, int, const Complex<double>*,
                                         Complex<double>*, hipStream_t);
 template hipError_t run_gf_step<float>(DevicePlan&, const gpe_params&, double, int, const Complex<float>*,
+                                       Complex<float>*, hipStream_t);
+template hipError_t run_ts_step<double>(DevicePlan&, const gpe_params&, double, double, const Complex<double>*,
+                                        Complex<double>*, hipStream_t);
+template hipError_t run_ts_step<float>(DevicePlan&, const gpe_params&, double, double, const Complex<float>*,
                                        Complex<float>*, hipStream_t);
 template int gpe_reduction_blocks<double>(const DevicePlan&);
 template int gpe_reduction_blocks<float>(const DevicePlan&);

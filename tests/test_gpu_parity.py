@@ -319,6 +319,67 @@ def test_gf_step_fp64_matches_oracle():
     assert relinf(out.cpu().numpy(), ref) < FP64_TOL
 
 
+# ---------------------------------------------------------------- GPE dynamics: time splitting (Eq. tssp2)
+def ts_state(n, L):
+    """A moving, asymmetric state (plane-wave phase times a skewed mixture), normalised."""
+    lumps, _ = I.mixture_lumps(0, len(n), (2, 2), centre=1.0, widths=(0.8, 1.5))
+    X = np.meshgrid(*I.grid_axes(n, L), indexing="ij")
+    psi = I.lumps_on_grid(lumps, n, L) * np.exp(1j * (0.7 * X[0] - 0.4 * X[-1])) * (1.0 + 0.3 * np.tanh(X[1]))
+    return I.normalise(psi, n, L)[0]
+
+
+@pytest.mark.parametrize("delta", [0.0, 0.7])
+def test_ts_step_fp64_matches_oracle(delta):
+    say(f"case: ts step 16^3 fp64 delta {delta}")
+    plan, prob, _, gp = gpe_case()
+    psi = ts_state(prob.n, prob.L)
+    out = plan.ts_step(to_dev(psi, torch.complex128), gp.beta, gp.lam, gp.gamma, dt=0.01, delta=delta)
+    ref = O.ts_step(psi, prob, gp, dt=0.01, delta=delta)
+    err = relinf(out.cpu().numpy(), ref)
+    say(f"  rel Linf = {err:.3e}")
+    assert err < FP64_TOL
+
+
+def test_ts_steps_fp64_in_place_and_reversible():
+    """Five steps in place against five oracle steps; then five steps of -dt return to the start."""
+    say("case: ts 5 steps 16^3 fp64, in place, reversed")
+    plan, prob, _, gp = gpe_case()
+    psi = ts_state(prob.n, prob.L)
+    x = to_dev(psi, torch.complex128)
+    ref = psi
+    for _ in range(5):
+        plan.ts_step(x, gp.beta, gp.lam, gp.gamma, dt=0.005, out=x)
+        ref = O.ts_step(ref, prob, gp, dt=0.005)
+    err = relinf(x.cpu().numpy(), ref)
+    say(f"  rel Linf after 5 steps = {err:.3e}")
+    assert err < FP64_TOL
+    for _ in range(5):
+        plan.ts_step(x, gp.beta, gp.lam, gp.gamma, dt=-0.005, out=x)
+    back = relinf(x.cpu().numpy(), psi)
+    say(f"  rel Linf after 5 steps back = {back:.3e}")
+    assert back < FP64_TOL
+
+
+def test_ts_step_2d_fp64_and_mixed():
+    say("case: ts step 2D 64^2 fp64 and 16^3 mixed")
+    n, L = (64, 64), (8.0, 8.0)
+    plan, prob = make(2, n, L, (32, 1, 64), dip_n=(math.sqrt(0.5), 0.0, math.sqrt(0.5)))
+    gp = O.GPEParams(beta=10.0, lam=8.0, gamma=(1.0, 1.5))
+    psi = ts_state(n, L)
+    out = plan.ts_step(to_dev(psi, torch.complex128), gp.beta, gp.lam, gp.gamma, dt=0.01, delta=0.2)
+    err = relinf(out.cpu().numpy(), O.ts_step(psi, prob, gp, dt=0.01, delta=0.2))
+    say(f"  2D rel Linf = {err:.3e}")
+    assert err < FP64_TOL
+    plan, prob, _, gp = gpe_case(prec="mixed")
+    psi32 = ts_state(prob.n, prob.L).astype(np.complex64)
+    out = plan.ts_step(to_dev(psi32, torch.complex64), gp.beta, gp.lam, gp.gamma, dt=0.01)
+    err = relinf(out.cpu().numpy().astype(np.complex128), O.ts_step(psi32.astype(np.complex128), prob, gp, dt=0.01))
+    say(f"  mixed rel Linf = {err:.3e}")
+    assert err < MIXED_TOL
+    with pytest.raises(DDIError):
+        plan.ts_step(to_dev(psi32, torch.complex64), gp.beta, gp.lam, gp.gamma, dt=0.01, delta=-1.0)
+
+
 def test_gpe_mixed_energy():
     say("case: gpe energy 16^3 mixed")
     plan, prob, psi, gp = gpe_case(prec="mixed")
