@@ -235,6 +235,32 @@ def other_workloads(args, torch, np, I, DDIPlan):
         "steps": wl["steps"], "ms_per_step": round(1000.0 * el / wl["steps"], 3),
         "energy_history": [[h[0], round(h[5], 8), round(h[7], 6)] for h in hist],
         "E_final": [float(v) for v in E], "energy_grad_ms": round(fa, 3)}
+
+    # dynamics from that ground state after the trap is tightened along x (gamma_x 1 -> 2)
+    print("[bench] c6_ts", file=sys.stderr, flush=True)
+    g2 = (2.0 * wl["gamma"][0],) + tuple(wl["gamma"][1:])
+    dt_ts, n_ts = 0.001, 100
+    x = psi.clone()
+    cell = p.cell
+    m0 = cell * float((x.abs() ** 2).sum())
+    E0 = p.energy_grad(x, wl["beta"], wl["lam"], g2, grad=False)[0][4]
+    for _ in range(3):
+        p.ts_step(psi, wl["beta"], wl["lam"], g2, dt=dt_ts, out=x)
+    x.copy_(psi)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n_ts):
+        p.ts_step(x, wl["beta"], wl["lam"], g2, dt=dt_ts, out=x)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    m1 = cell * float((x.abs() ** 2).sum())
+    E1 = p.energy_grad(x, wl["beta"], wl["lam"], g2, grad=False)[0][4]
+    res["c6_time_splitting"] = {
+        "workload": "c6_ts: 3D dipolar GPE dynamics by time splitting (gpe_ts_step), 128^3 on [-8,8)^3, "
+                    "from the c5 ground state with the trap tightened to gamma=(2,1,5), beta=200, lambda=150, "
+                    "dt=0.001, 100 steps, FP64",
+        "steps": n_ts, "ms_per_step": round(1000.0 * el / n_ts, 3),
+        "mass_rel_change": m1 / m0 - 1.0, "energy_rel_change": E1 / E0 - 1.0}
     return res
 
 
