@@ -261,6 +261,27 @@ def other_workloads(args, torch, np, I, DDIPlan):
                     "dt=0.001, 100 steps, FP64",
         "steps": n_ts, "ms_per_step": round(1000.0 * el / n_ts, 3),
         "mass_rel_change": m1 / m0 - 1.0, "energy_rel_change": E1 / E0 - 1.0}
+    del p, psi, x
+
+    # the paper's Table 7, row lambda = beta = 207.16: ground state with converged inner solves
+    print("[bench] c7_table7", file=sys.stderr, flush=True)
+    gam7, beta7 = (1.0, 1.0, 0.5), 207.16
+    n7, L7 = (128,) * 3, (12.0,) * 3
+    p = DDIPlan(3, n7, L7, dip_n=(0.0, 0.0, 1.0), quad=(96, 48, 96), tol=1e-13, prec="fp64")
+    psi0 = torch.from_numpy(I.gf_initial(n7, L7, gam7)).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, hist = ground_state(p, psi0, beta7, beta7, gam7, dt=0.02, steps=3000, n_inner=30, energy_every=100, eps0=1e-9)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    step, ek, ep, ei, ed, E, mu, r = hist[-1]
+    res["c7_table7_ground_state"] = {
+        "workload": "Table 7 row lambda = 207.16: 3D ground state, beta = 207.16, V=(x^2+y^2+z^2/4)/2, n=z, "
+                    "[-12,12)^3 at 128^3, gradient flow dt = 0.02 with 30 inner iterations, until residual 1e-9",
+        "steps": int(step), "seconds": round(el, 3), "residual": r,
+        "ours": {"E": E, "mu": mu, "kin": ek, "pot": ep, "int": ei, "dip": ed,
+                 "virial": 2 * ek - 2 * ep + 3 * ei + 3 * ed},
+        "paper": {"E": 2.1838, "mu": 2.7011, "kin": 0.44525, "pot": 1.2212, "int": 1.5749, "dip": -1.0576}}
     return res
 
 
