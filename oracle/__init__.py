@@ -11,8 +11,11 @@ Contents
 ``ddi_oracle``  plain FP64 evaluation of the spherical/polar Fourier quadrature
                 of the DDI (Bao, Tang & Zhang, Sec. 2.1, Eqs. DDI-Con and
                 DDI-Trun1) by direct nonuniform DFTs, its literal adjoint, the
-                GPE energy split and gradient (Sec. 3.2) and one gradient-flow
-                step (Sec. 3.1, Eqs. gf-eq2, gf-colb2, gffg33).
+                GPE energy split and gradient (Sec. 3.2), one gradient-flow
+                step (Sec. 3.1, Eqs. gf-eq2, gf-colb2, gffg33), one time-splitting
+                step (Sec. 4.1, Eq. tssp2) and the split I_1 + I_2 of Eq. 3.9
+                (3D: the short-range part by the zero-padded FFT, the long-range
+                part by direct sums over a small ball).
 ``refs``        analytic references used to pin the oracle: the 3D Gaussian
                 closed form (Ex. 2.1, Eqs. extDensGausDipolar and Hessian_Ex1),
                 the 2D Gaussian Bessel form (Ex. 2.2) and the 1D heat-kernel
