@@ -81,6 +81,25 @@ typedef enum { DDI_FP64 = 0, DDI_MIXED = 1 } ddi_precision;
  *  prec         DDI_FP64 or DDI_MIXED (FP32 grids, spread, interp and FFT).
  *  kernel_width 0 = from tol; else the width w (4..16) of the
  *               exponential-of-semicircle kernel.
+ *  split        0: the quadrature over the whole ball (above).  1 (3D only;
+ *               2D returns DDI_ENOTSUP): the split of Sec. 2.1, Eq. 3.9,
+ *               Phi = I_1 + I_2 with the partition q(k) = exp(-|k|^2/s^2):
+ *                 I_1 = (2 pi)^-3 int over the Nyquist box |k_i| < pi/h_i of
+ *                       exp(i k.x) (1 - q(k)) Uhat(k) rhohat(k) dk, by the
+ *                       trapezoid rule of the box zero-padded to 2 n_i points
+ *                       per axis (k_m = pi m / (2 L_i), |m| < n_i; the Nyquist
+ *                       planes m_i = -n_i are left out), i.e. a padded FFT,
+ *                       a multiplication and an inverse FFT;
+ *                 I_2 = the quadrature sum above over the ball of radius kmax
+ *                       with every weight c_q multiplied by q(k_q).
+ *               The quadrature sizes and kmax are then those of I_2, and
+ *               kmax <= 0 selects s sqrt(ln(1/tol)).  ddi_type2 / ddi_type1
+ *               act on the I_2 nodes.
+ *  split_s      s of the partition (split = 1); <= 0 selects
+ *               sqrt(ln(1/tol)) / min_i L_i, which puts the decay
+ *               exp(-s^2 r^2/4) of the short-range kernel at tol at the
+ *               nearest image 2 L_min away.  With kernel_width set and tol
+ *               outside (0, 1), tol is taken as 10^-(w-1).
  */
 typedef struct {
   int32_t dim;
@@ -94,6 +113,8 @@ typedef struct {
   double tol;
   int32_t prec;
   int32_t kernel_width;
+  int32_t split;
+  double split_s;
 } ddi_params;
 
 /*
@@ -123,6 +144,8 @@ typedef struct {
   int64_t spread_items; /* spread work items (tiles and tile chunks) */
   int64_t spread_entries; /* (tile, node) pairs visited by one spread */
   int64_t workspace_bytes;
+  int32_t split;        /* 1 for the split of Eq. 3.9 */
+  double split_s;       /* s of the partition as used (0 without the split) */
 } ddi_plan_info_t;
 
 /* Build a plan: quadrature nodes and weights, mask, symbol, kernel and
@@ -130,12 +153,15 @@ typedef struct {
  * Synchronises `stream` before returning.  *out is NULL on failure. */
 ddi_status ddi_plan(const ddi_params* params, void* stream, ddi_plan_t* out);
 
-/* Phi = A rho (Sec. 2.1, Eqs. DDI-Con, DDI-Trun1).  rho_dev, phi_dev: real grids. */
+/* Phi = A rho (Sec. 2.1, Eqs. DDI-Con, DDI-Trun1).  rho_dev, phi_dev: real grids.
+ * A split plan returns I_1 + I_2 (Eq. 3.9): the I_2 quadrature sum, then I_1 added to it. */
 ddi_status ddi_apply(ddi_plan_t plan, const void* rho_dev, void* phi_dev, void* stream);
 
 /* rhobar = A^T phibar, executed literally: transform with exp(+i k.x) to the
  * nodes, weights c_q, transform back with exp(-i k.x), real part.  In exact
- * arithmetic A^T = A; used for gradients. */
+ * arithmetic A^T = A; used for gradients.  A split plan returns the transpose of
+ * I_2 plus I_1 (the padded convolution with an even real multiplier over a
+ * symmetric set of modes is its own transpose). */
 ddi_status ddi_apply_adjoint(ddi_plan_t plan, const void* phibar_dev, void* rhobar_dev, void* stream);
 
 /* Type-2 half: rhohat_q = prod(h) sum_l rho_l exp(-i k_q . x_l) for the M_eff
@@ -197,8 +223,9 @@ ddi_status gpe_ts_step(ddi_plan_t plan, const gpe_params* gp, double dt, double 
  *   2 axis-0 FFT (pruned; 0 in 2D)                        7 axis-1 FFT (pruned)
  *   3 interpolation at the nodes and weighting            8 last-axis FFT, truncation,
  *   4 spread to the fine grid                               deconvolution and real part
- * The outputs are the same as those of ddi_apply / ddi_apply_adjoint.
- * Synchronises `stream`.
+ * The outputs are the same as those of ddi_apply / ddi_apply_adjoint.  For a
+ * split plan the stages are those of I_2; I_1 runs after stage 8 and is not
+ * timed.  Synchronises `stream`.
  */
 #define DDI_NSTAGES 9
 ddi_status ddi_profile_apply(ddi_plan_t plan, const void* in_dev, void* out_dev, int32_t sign, int32_t reps,

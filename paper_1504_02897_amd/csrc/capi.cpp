@@ -44,7 +44,7 @@ hipError_t upload(X** dst, const X* src, size_t count, hipStream_t s, int64_t& b
 }
 
 void free_plan(ddi::DevicePlan& P) {
-  void* ptrs[] = {P.nodes, P.c_scaled, P.c_half, P.deconv[0], P.deconv[1], P.deconv[2],
+  void* ptrs[] = {P.nodes, P.c_scaled, P.c_half, P.ones, P.deconv[0], P.deconv[1], P.deconv[2],
                   P.fine, P.gnodes, P.partial, P.ipartial, P.pads, P.gpe_rho, P.gpe_phi, P.gpe_phit, P.gpe_c1, P.gpe_c2, P.gpe_red};
   for (auto& d : P.dsched) {
     void* sp[] = {d.list, d.items, d.reduces, d.interp_items, d.interp_direct, d.gptr, d.gpos, d.ent};
@@ -81,6 +81,10 @@ ddi_status build_device(ddi::DevicePlan& P, hipStream_t s, std::vector<ddi::Node
   HIP_TRY(upload(&P.c_half, cs_half.data(), cs_half.size(), s, bytes), "upload weights");
   for (int a = 0; a < 3; ++a)
     HIP_TRY(upload(&P.deconv[a], H.deconv[a].data(), H.deconv[a].size(), s, bytes), "upload deconvolution");
+  if (H.split) {
+    const std::vector<double> ones(std::max(H.N[0], std::max(H.N[1], H.N[2])), 1.0);
+    HIP_TRY(upload(&P.ones, ones.data(), ones.size(), s, bytes), "upload unit factors");
+  }
   // tile-owned interpolation (FP64 in 3D) and the weight rows of the matrix-core kernels
   const bool tile_interp = ddi::interp_is_tiled(H, sizeof(T) == 8);
   const bool use_pads = ddi::uses_weight_rows(H);
@@ -265,6 +269,8 @@ ddi_status ddi_plan_info(ddi_plan_t plan, ddi_plan_info_t* info) {
   info->spread_items = static_cast<int64_t>(H.sched[ddi::kHalf].items.size());
   info->spread_entries = static_cast<int64_t>(H.sched[ddi::kHalf].list.size());
   info->workspace_bytes = plan->P.workspace_bytes;
+  info->split = H.split ? 1 : 0;
+  info->split_s = H.split_s;
   return DDI_OK;
 }
 
@@ -283,8 +289,8 @@ ddi_status ddi_apply(ddi_plan_t plan, const void* rho_dev, void* phi_dev, void* 
   if (!rho_dev || !phi_dev) return fail(DDI_EINVAL, "NULL buffer");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   ddi::DevicePlan& P = plan->P;
-  hipError_t e = P.mixed ? ddi::run_apply<float>(P, static_cast<const float*>(rho_dev), static_cast<float*>(phi_dev), +1, s, nullptr)
-                         : ddi::run_apply<double>(P, static_cast<const double*>(rho_dev), static_cast<double*>(phi_dev), +1, s, nullptr);
+  hipError_t e = P.mixed ? ddi::run_ddi<float>(P, static_cast<const float*>(rho_dev), static_cast<float*>(phi_dev), +1, s, nullptr)
+                         : ddi::run_ddi<double>(P, static_cast<const double*>(rho_dev), static_cast<double*>(phi_dev), +1, s, nullptr);
   if (e != hipSuccess) return hip_fail(e, "ddi_apply launch");
   return DDI_OK;
 }
@@ -295,8 +301,8 @@ ddi_status ddi_apply_adjoint(ddi_plan_t plan, const void* phibar_dev, void* rhob
   if (!phibar_dev || !rhobar_dev) return fail(DDI_EINVAL, "NULL buffer");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   ddi::DevicePlan& P = plan->P;
-  hipError_t e = P.mixed ? ddi::run_apply<float>(P, static_cast<const float*>(phibar_dev), static_cast<float*>(rhobar_dev), -1, s, nullptr)
-                         : ddi::run_apply<double>(P, static_cast<const double*>(phibar_dev), static_cast<double*>(rhobar_dev), -1, s, nullptr);
+  hipError_t e = P.mixed ? ddi::run_ddi<float>(P, static_cast<const float*>(phibar_dev), static_cast<float*>(rhobar_dev), -1, s, nullptr)
+                         : ddi::run_ddi<double>(P, static_cast<const double*>(phibar_dev), static_cast<double*>(rhobar_dev), -1, s, nullptr);
   if (e != hipSuccess) return hip_fail(e, "ddi_apply_adjoint launch");
   return DDI_OK;
 }
@@ -321,8 +327,8 @@ ddi_status ddi_profile_apply(ddi_plan_t plan, const void* in_dev, void* out_dev,
   for (int i = 0; i < ddi::kStages; ++i) stage_ms[i] = 0.0;
   ddi_status result = DDI_OK;
   for (int r = 0; r < reps && result == DDI_OK; ++r) {
-    hipError_t e = P.mixed ? ddi::run_apply<float>(P, static_cast<const float*>(in_dev), static_cast<float*>(out_dev), sign, s, ev)
-                           : ddi::run_apply<double>(P, static_cast<const double*>(in_dev), static_cast<double*>(out_dev), sign, s, ev);
+    hipError_t e = P.mixed ? ddi::run_ddi<float>(P, static_cast<const float*>(in_dev), static_cast<float*>(out_dev), sign, s, ev)
+                           : ddi::run_ddi<double>(P, static_cast<const double*>(in_dev), static_cast<double*>(out_dev), sign, s, ev);
     if (e == hipSuccess) e = hipEventSynchronize(ev[ddi::kStages]);
     if (e != hipSuccess) { result = hip_fail(e, "ddi_profile_apply"); break; }
     for (int i = 0; i < ddi::kStages; ++i) {

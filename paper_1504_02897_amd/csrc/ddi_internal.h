@@ -164,6 +164,11 @@ struct HostTables {
   // (the strided FFT passes cover a window in blocks of lines that divide it: 128-byte rows)
   int zalign = 16;
   Schedule sched[2];
+  // split of Eq. 3.9 (3D): c holds the I_2 weights (times q); I_1 uses the axes and s
+  bool split = false;
+  double split_s = 0.0;
+  double nv[3] = {0, 0, 1};
+  double mv[3] = {0, 0, 1};
 };
 
 // Kernel selection shared by the plan upload and the drivers.
@@ -208,6 +213,7 @@ struct DevicePlan {
   double* c_scaled = nullptr;    // c_q * prod(h) [M]
   double* deconv[3] = {nullptr, nullptr, nullptr};
   double* c_half = nullptr;       // half_factor * c_q * prod(h) [M]
+  double* ones = nullptr;         // [max N]: unit factors for the split's padded FFT passes
   struct DevSchedule {
     int32_t* list = nullptr;
     SpreadItem* items = nullptr;
@@ -247,6 +253,12 @@ hipError_t run_type1(DevicePlan& P, int which, const Complex<T>* g, T* phi, int 
                      hipEvent_t* ev);
 template <typename T>
 hipError_t run_apply(DevicePlan& P, const T* rho, T* phi, int sign, hipStream_t s, hipEvent_t* ev);
+// I_1 of the split (Eq. 3.9) added to phi: padded FFT, (1 - q) Uhat, inverse FFT.
+template <typename T>
+hipError_t run_split_short(DevicePlan& P, const T* rho, T* phi, hipStream_t s);
+// The operator of the plan: run_apply, plus I_1 for a split plan (I_1 is its own transpose).
+template <typename T>
+hipError_t run_ddi(DevicePlan& P, const T* rho, T* phi, int sign, hipStream_t s, hipEvent_t* ev);
 constexpr int kStages = 9;
 template <typename T>
 hipError_t run_gpe_energy_grad(DevicePlan& P, const gpe_params& gp, const Complex<T>* psi, double* E_dev,

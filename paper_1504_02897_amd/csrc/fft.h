@@ -9,7 +9,17 @@ namespace ddi {
 // factors into the active half of each oversampled line; C2C is a plain complex
 // transform; C2R_TRUNC keeps the active modes, applies the deconvolution factors
 // and writes the real part to a compact grid.
-enum ContigMode { R2C_PAD = 0, C2C = 1, C2R_TRUNC = 2 };
+enum ContigMode { R2C_PAD = 0, C2C = 1, C2R_TRUNC = 2, C2R_ADD = 3 };   // C2R_ADD: as C2R_TRUNC, added to the output
+
+// The multiplier of the split's short-range part (Eq. 3.9) on the zero-padded grid:
+// (1 - exp(-|k|^2/s^2)) (3 (n.k)(m.k)/|k|^2 - n.m) at k_i = m_i dk[i], times scale.
+struct SplitSymbol {
+  double n[3], m[3];
+  double nm;
+  double inv_s2;
+  double dk[3];
+  double scale;
+};
 
 // In-place transforms of length n along axis 0 or 1 of a [d0][d1][d2] complex
 // array.  The other non-last axis runs over n_o lines (the compact modes of an
@@ -30,6 +40,15 @@ template <typename T, int SIGN, int MODE>
 hipError_t launch_contig(int n, const void* in, void* out, int n0, int n1, int d0, int d1, int nc2, int z0, int nz,
                          const double* D0, const double* D1, const double* D2, const Complex<T>* tw,
                          hipStream_t s);
+
+// Lines along axis 0 of the [d0][d1][d2] padded spectrum of a real field, at last-axis
+// positions [0, nz) (the modes m2 in [0, nz), nz <= d2/2): transform the nc active inputs
+// with exp(-2 pi i jk/n), multiply by the split symbol times 1 at m2 = 0 and 2 above (the
+// half set; the partner modes are the complex conjugates), zero on the Nyquist planes
+// m_i = -d_i/2, transform back with exp(+2 pi i jk/n) and write the nc active outputs.
+template <typename T>
+hipError_t launch_symbol(int n, Complex<T>* F, int d1, int d2, int nc, int nz, const SplitSymbol& sp,
+                         const Complex<T>* tw, hipStream_t s);
 
 inline int ilog2(int n) {
   int l = 0;

@@ -244,6 +244,94 @@ __global__ void __launch_bounds__(MAXT) k_fft_strided(C<T>* __restrict__ F, int 
   }
 }
 
+// ------------------------------------------------------------------ split: axis-0 pass with the symbol
+// Moves a line from the output distribution of line_fft (thread j0 holds k = LineOut::k(j0, i)
+// in v[i]) to its input distribution (v[r] = x[j0 + r*TL]) through LDS.  Ends with a barrier,
+// so the next line_fft may write LDS at once.
+template <typename T, int N, typename P, typename Addr>
+__device__ __forceinline__ void line_to_natural(LdsElem<T, N>* lds, Addr addr, int j0, C<T>* v) {
+  constexpr int TL = N / P::R1;
+  C<T> w[P::R1];
+  if constexpr (SplitExchange<T, N>::value) {
+#pragma unroll
+    for (int part = 0; part < 2; ++part) {
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < P::R1; ++i) lds[addr(LineOut<P, N>::k(j0, i))] = part == 0 ? v[i].re : v[i].im;
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < P::R1; ++r) {
+        const T x = lds[addr(j0 + r * TL)];
+        if (part == 0) w[r].re = x;
+        else w[r].im = x;
+      }
+    }
+  } else {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < P::R1; ++i) lds[addr(LineOut<P, N>::k(j0, i))] = v[i];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < P::R1; ++r) w[r] = lds[addr(j0 + r * TL)];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < P::R1; ++r) v[r] = w[r];
+}
+
+// Lines (., y, z) of the padded spectrum for y in [0, d1) and z in [0, nz); B consecutive z per
+// workgroup.  See launch_symbol.
+template <typename T, int N, int MAXT>
+__global__ void __launch_bounds__(MAXT) k_fft_symbol(C<T>* __restrict__ F, int d1, int d2, int nc_axis, int nzb,
+                                                    SplitSymbol sp, const C<T>* __restrict__ tw, int B) {
+  extern __shared__ unsigned char smem_raw[];
+  LdsElem<T, N>* lds = reinterpret_cast<LdsElem<T, N>*>(smem_raw);
+  using P = Radix<T, N, false>;
+  constexpr int TL = N / P::R1;
+  const int b = threadIdx.x % B;
+  const int j0 = threadIdx.x / B;
+  const int y = blockIdx.x / nzb;
+  const int z = (blockIdx.x % nzb) * B + b;
+  const int64_t base = static_cast<int64_t>(y) * d2 + z;
+  const int64_t stride = static_cast<int64_t>(d1) * d2;
+  auto addr = [B, b](int k) { return k * B + b; };
+  C<T> v[P::R1];
+#pragma unroll
+  for (int r = 0; r < P::R1; ++r) {
+    const int k = j0 + r * TL;
+    v[r] = active(k, N, nc_axis) ? F[base + k * stride] : C<T>{0, 0};
+  }
+  line_fft<T, N, -1, P>(lds, addr, j0, tw, v);
+  // modes: m1 signed from y (Nyquist plane y = d1/2 dropped); m2 = z in [0, d2/2)
+  const bool nyq1 = 2 * y == d1;
+  const double k1 = (y < d1 / 2 ? y : y - d1) * sp.dk[1];
+  const double k2 = z * sp.dk[2];
+  const double w2 = z == 0 ? sp.scale : 2.0 * sp.scale;
+  const double kn12 = k1 * sp.n[1] + k2 * sp.n[2];
+  const double km12 = k1 * sp.m[1] + k2 * sp.m[2];
+  const double u12 = k1 * k1 + k2 * k2;
+#pragma unroll
+  for (int i = 0; i < P::R1; ++i) {
+    const int k = LineOut<P, N>::k(j0, i);
+    const double k0 = (k < N / 2 ? k : k - N) * sp.dk[0];
+    const double u = k0 * k0 + u12;
+    double mult = 0.0;
+    if (!nyq1 && 2 * k != N && u > 0.0) {
+      const double kn = k0 * sp.n[0] + kn12;
+      const double km = k0 * sp.m[0] + km12;
+      mult = -expm1(-u * sp.inv_s2) * (3.0 * kn * km / u - sp.nm) * w2;
+    }
+    v[i] = C<T>{static_cast<T>(v[i].re * mult), static_cast<T>(v[i].im * mult)};
+  }
+  line_to_natural<T, N, P>(lds, addr, j0, v);
+  line_fft<T, N, 1, P>(lds, addr, j0, tw, v);
+#pragma unroll
+  for (int i = 0; i < P::R1; ++i) {
+    const int k = LineOut<P, N>::k(j0, i);
+    if (active(k, N, nc_axis)) F[base + k * stride] = v[i];
+  }
+}
+
 // ------------------------------------------------------------------ last-axis (contiguous) FFT pass
 
 
@@ -300,7 +388,7 @@ __global__ void __launch_bounds__(256) k_fft_contig(const void* in, void* out,
   }
   line_fft<T, N, SIGN, P>(my, addr, j0, tw, v);
   if (!valid) return;
-  if (MODE == C2R_TRUNC) {
+  if (MODE == C2R_TRUNC || MODE == C2R_ADD) {
     T* phi = reinterpret_cast<T*>(out);
     const double s01 = D0[o0] * D1[o1];
     const int64_t rb = (static_cast<int64_t>(o0) * n1 + o1) * nc2;
@@ -309,7 +397,9 @@ __global__ void __launch_bounds__(256) k_fft_contig(const void* in, void* out,
       const int k = LineOut<P, N>::k(j0, i);
       if (active(k, N, nc2)) {
         const int c2 = cmap(k, N, nc2);
-        phi[rb + c2] = static_cast<T>(static_cast<double>(v[i].re) * s01 * D2[c2]);
+        const T val = static_cast<T>(static_cast<double>(v[i].re) * s01 * D2[c2]);
+        if (MODE == C2R_ADD) phi[rb + c2] += val;
+        else phi[rb + c2] = val;
       }
     }
   } else {
@@ -365,6 +455,41 @@ hipError_t launch_strided(int n, C<T>* F, int axis, int d0, int d1, int d2, int 
     case 256: return launch_strided_n<T, 256, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, z0, nz, tw, s);
     case 512: return launch_strided_n<T, 512, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, z0, nz, tw, s);
     case 1024: return launch_strided_n<T, 1024, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, z0, nz, tw, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T, int N>
+static hipError_t launch_symbol_n(C<T>* F, int d1, int d2, int nc, int nz, const SplitSymbol& sp, const C<T>* tw,
+                                  hipStream_t s) {
+  constexpr int TL = N / Radix<T, N, false>::R1;
+  int B = 256 / TL;   // as in the strided pass: >= 128-byte row segments where LDS allows
+  while (B * static_cast<int>(sizeof(C<T>)) < 128 && 2 * B * TL <= 1024 &&
+         static_cast<size_t>(2 * B) * N * sizeof(LdsElem<T, N>) <= 65536)
+    B *= 2;
+  while (B > 1 && nz % B != 0) B >>= 1;
+  if (nz <= 0 || 2 * nz > d2 || nz % B != 0 || nc > N || nc < 1) return hipErrorInvalidValue;
+  const size_t shm = static_cast<size_t>(B) * N * sizeof(LdsElem<T, N>);
+  const int nzb = nz / B;
+  const int blocks = d1 * nzb;
+  if (B * TL <= 256)
+    hipLaunchKernelGGL((k_fft_symbol<T, N, 256>), dim3(blocks), dim3(B * TL), shm, s, F, d1, d2, nc, nzb, sp, tw, B);
+  else
+    hipLaunchKernelGGL((k_fft_symbol<T, N, 1024>), dim3(blocks), dim3(B * TL), shm, s, F, d1, d2, nc, nzb, sp, tw, B);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_symbol(int n, C<T>* F, int d1, int d2, int nc, int nz, const SplitSymbol& sp, const C<T>* tw,
+                         hipStream_t s) {
+  switch (n) {
+    case 16: return launch_symbol_n<T, 16>(F, d1, d2, nc, nz, sp, tw, s);
+    case 32: return launch_symbol_n<T, 32>(F, d1, d2, nc, nz, sp, tw, s);
+    case 64: return launch_symbol_n<T, 64>(F, d1, d2, nc, nz, sp, tw, s);
+    case 128: return launch_symbol_n<T, 128>(F, d1, d2, nc, nz, sp, tw, s);
+    case 256: return launch_symbol_n<T, 256>(F, d1, d2, nc, nz, sp, tw, s);
+    case 512: return launch_symbol_n<T, 512>(F, d1, d2, nc, nz, sp, tw, s);
+    case 1024: return launch_symbol_n<T, 1024>(F, d1, d2, nc, nz, sp, tw, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -425,5 +550,11 @@ DDI_INST_CONTIG(double, 1, C2R_TRUNC)
 DDI_INST_CONTIG(double, -1, C2R_TRUNC)
 DDI_INST_CONTIG(float, 1, C2R_TRUNC)
 DDI_INST_CONTIG(float, -1, C2R_TRUNC)
+DDI_INST_CONTIG(double, 1, C2R_ADD)
+DDI_INST_CONTIG(float, 1, C2R_ADD)
+template hipError_t launch_symbol<double>(int, C<double>*, int, int, int, int, const SplitSymbol&, const C<double>*,
+                                          hipStream_t);
+template hipError_t launch_symbol<float>(int, C<float>*, int, int, int, int, const SplitSymbol&, const C<float>*,
+                                         hipStream_t);
 
 }  // namespace ddi

@@ -350,7 +350,7 @@ hipError_t run_gpe_energy_grad(DevicePlan& P, const gpe_params& gp, const Comple
   double* red_terms = P.gpe_red + 4 * nb;
   hipLaunchKernelGGL((k_density<T>), dim3(ew_blocks(n)), dim3(256), 0, s, psi, rho, n);
   DDI_CHECK(hipGetLastError());
-  DDI_CHECK(run_apply<T>(P, rho, phi, +1, s, nullptr));
+  DDI_CHECK(run_ddi<T>(P, rho, phi, +1, s, nullptr));
   hipLaunchKernelGGL((k_copy<T>), dim3(ew_blocks(n)), dim3(256), 0, s, psi, c1, n);
   DDI_CHECK(hipGetLastError());
   DDI_CHECK((fft3_full<T, -1>(P, c1, s)));
@@ -362,7 +362,7 @@ hipError_t run_gpe_energy_grad(DevicePlan& P, const gpe_params& gp, const Comple
                      gp.lambda, E_dev);
   DDI_CHECK(hipGetLastError());
   if (grad) {
-    DDI_CHECK(run_apply<T>(P, rho, phit, -1, s, nullptr));
+    DDI_CHECK(run_ddi<T>(P, rho, phit, -1, s, nullptr));
     DDI_CHECK((fft3_full<T, +1>(P, c1, s)));     // c1 = -1/2 Lap psi
     hipLaunchKernelGGL((k_grad<T>), dim3(ew_blocks(n)), dim3(256), 0, s, psi, c1, rho, phi, phit, Vext, n, G, H.cell,
                        gp.beta, gp.lambda, grad);
@@ -389,7 +389,7 @@ hipError_t run_gf_step(DevicePlan& P, const gpe_params& gp, double dt, int n_inn
   double* scal = P.gpe_red + 8 * nb;
   hipLaunchKernelGGL((k_density<T>), dim3(ew_blocks(n)), dim3(256), 0, s, psi_in, rho, n);
   DDI_CHECK(hipGetLastError());
-  DDI_CHECK(run_apply<T>(P, rho, phi, +1, s, nullptr));
+  DDI_CHECK(run_ddi<T>(P, rho, phi, +1, s, nullptr));
   hipLaunchKernelGGL((k_gf_coeff<T>), dim3(nb), dim3(kRedThreads), 0, s, rho, phi, Vext, n, G, gp.beta, gp.lambda,
                      Bc, red);
   DDI_CHECK(hipGetLastError());
@@ -450,7 +450,7 @@ hipError_t run_ts_step(DevicePlan& P, const gpe_params& gp, double dt, double de
   DDI_CHECK(half_kinetic());
   hipLaunchKernelGGL((k_density<T>), dim3(ew_blocks(n)), dim3(256), 0, s, psi_out, rho, n);
   DDI_CHECK(hipGetLastError());
-  if (gp.lambda != 0.0) DDI_CHECK(run_apply<T>(P, rho, phi, +1, s, nullptr));
+  if (gp.lambda != 0.0) DDI_CHECK(run_ddi<T>(P, rho, phi, +1, s, nullptr));
   hipLaunchKernelGGL((k_ts_potential<T>), dim3(ew_blocks(n)), dim3(256), 0, s, psi_out, rho,
                      gp.lambda != 0.0 ? phi : rho, Vext, n, G, dt, sfac, gp.beta, gp.lambda, std::exp(-delta * dt));
   DDI_CHECK(hipGetLastError());

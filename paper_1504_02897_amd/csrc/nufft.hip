@@ -956,6 +956,51 @@ hipError_t run_apply(DevicePlan& P, const T* rho, T* phi, int sign, hipStream_t 
   return run_type1<T>(P, kHalf, g, phi, sign, s, ev);
 }
 
+// I_1 of the split (Eq. 3.9), added to phi.  The box is zero-padded to the fine grid (2 N_i
+// points, k_m = 2 pi m / (2 N_i h_i)); the density enters without deconvolution.  Only the modes
+// m2 in [0, N2) are formed (a real field's half set; m2 = -N2 is a Nyquist plane): last-axis
+// FFT with padding, axis-1 FFT, then one pass that transforms axis 0, multiplies by
+// (1 - q) Uhat and transforms back, axis-1 inverse, last-axis inverse with truncation, real
+// part and accumulation.
+template <typename T>
+hipError_t run_split_short(DevicePlan& P, const T* rho, T* phi, hipStream_t s) {
+  const HostTables& H = P.H;
+  if (!H.split || H.dim != 3 || !P.ones) return hipErrorInvalidValue;
+  C<T>* F = reinterpret_cast<C<T>*>(P.fine);
+  const int nz = H.N[2];
+  const C<T>* tw0 = reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[0])]);
+  const C<T>* tw1 = reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[1])]);
+  const C<T>* tw2 = reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[2])]);
+  SplitSymbol sp;
+  for (int i = 0; i < 3; ++i) {
+    sp.n[i] = H.nv[i];
+    sp.m[i] = H.mv[i];
+    sp.dk[i] = 2.0 * M_PI / (H.nf[i] * H.h[i]);
+  }
+  sp.nm = H.nv[0] * H.mv[0] + H.nv[1] * H.mv[1] + H.nv[2] * H.mv[2];
+  sp.inv_s2 = 1.0 / (H.split_s * H.split_s);
+  sp.scale = 1.0 / (static_cast<double>(H.nf[0]) * H.nf[1] * H.nf[2]);
+  DDI_CHECK((launch_contig<T, -1, R2C_PAD>(H.nf[2], rho, F, H.N[0], H.N[1], H.nf[0], H.nf[1], H.N[2], 0, nz, P.ones,
+                                           P.ones, P.ones, tw2, s)));
+  DDI_CHECK((launch_strided<T, -1>(H.nf[1], F, 1, H.nf[0], H.nf[1], H.nf[2], H.N[0], 1, H.N[1], 1, 0, 0, nz, tw1, s)));
+  DDI_CHECK((launch_symbol<T>(H.nf[0], F, H.nf[1], H.nf[2], H.N[0], nz, sp, tw0, s)));
+  DDI_CHECK((launch_strided<T, 1>(H.nf[1], F, 1, H.nf[0], H.nf[1], H.nf[2], H.N[0], 1, H.N[1], 0, 1, 0, nz, tw1, s)));
+  DDI_CHECK((launch_contig<T, 1, C2R_ADD>(H.nf[2], F, phi, H.N[0], H.N[1], H.nf[0], H.nf[1], H.N[2], 0, nz, P.ones,
+                                          P.ones, P.ones, tw2, s)));
+  return hipSuccess;
+}
+
+template <typename T>
+hipError_t run_ddi(DevicePlan& P, const T* rho, T* phi, int sign, hipStream_t s, hipEvent_t* ev) {
+  DDI_CHECK(run_apply<T>(P, rho, phi, sign, s, ev));
+  if (P.H.split) DDI_CHECK(run_split_short<T>(P, rho, phi, s));
+  return hipSuccess;
+}
+
+template hipError_t run_split_short<double>(DevicePlan&, const double*, double*, hipStream_t);
+template hipError_t run_split_short<float>(DevicePlan&, const float*, float*, hipStream_t);
+template hipError_t run_ddi<double>(DevicePlan&, const double*, double*, int, hipStream_t, hipEvent_t*);
+template hipError_t run_ddi<float>(DevicePlan&, const float*, float*, int, hipStream_t, hipEvent_t*);
 template hipError_t run_type2<double>(DevicePlan&, int, const double*, Complex<double>*, const double*, double,
                                       int, hipStream_t, hipEvent_t*);
 template hipError_t run_type2<float>(DevicePlan&, int, const float*, Complex<float>*, const double*, double, int,

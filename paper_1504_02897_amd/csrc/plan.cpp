@@ -323,8 +323,11 @@ std::string build_tables(const ddi_params& p, HostTables& t, int* status) {
     w = std::min(kWMax, std::max(4, w));
   }
   if (w < 2 || w > kWMax) return "kernel_width must lie in [2, 16]";
+  if (p.split != 0 && p.split != 1) return "split must be 0 or 1";
+  if (p.split && !std::isfinite(p.split_s)) return "split_s must be finite";
 
   *status = DDI_ENOTSUP;
+  if (p.split && d != 3) return "the split of Eq. 3.9 is built for 3D only";
   // internal 3-axis layout: 2D grids live on axes 1 and 2
   const int off = 3 - d;
   for (int a = 0; a < 3; ++a) { t.N[a] = 1; t.nf[a] = 1; t.W[a] = 1; t.h[a] = 1.0; t.L[a] = 0.5; }
@@ -354,11 +357,28 @@ std::string build_tables(const ddi_params& p, HostTables& t, int* status) {
   // ---------------------------------------------------------------- quadrature
   double hp[3] = {0, 0, 0};      // h in paper axes
   for (int a = 0; a < d; ++a) hp[a] = 2.0 * p.L[a] / p.n[a];
+  // split (Eq. 3.9): I_1's kernel, the inverse transform of (1 - q) Uhat, decays like
+  // exp(-s^2 r^2 / 4) and the nearest image of the zero-padded box lies 2 L_min away, so
+  // s^2 L_min^2 = ln(1/tol); q rhohat falls below tol at |k| = s sqrt(ln(1/tol)).
+  double split_s = 0.0, ln_tol = 0.0;
+  if (p.split) {
+    const double tol_eff = (p.tol > 0.0 && p.tol < 1.0) ? p.tol : std::pow(10.0, -(w - 1));
+    ln_tol = std::log(1.0 / tol_eff);
+    double lmin = p.L[0];
+    for (int a = 1; a < d; ++a) lmin = std::min(lmin, p.L[a]);
+    split_s = p.split_s > 0.0 ? p.split_s : std::sqrt(ln_tol) / lmin;
+  }
+  t.split = p.split != 0;
+  t.split_s = split_s;
   double kmax = p.kmax;
   if (!(kmax > 0.0)) {
-    double s = 0.0;
-    for (int a = 0; a < d; ++a) s += 1.0 / (hp[a] * hp[a]);
-    kmax = M_PI * std::sqrt(s);
+    if (p.split) {
+      kmax = split_s * std::sqrt(ln_tol);
+    } else {
+      double s = 0.0;
+      for (int a = 0; a < d; ++a) s += 1.0 / (hp[a] * hp[a]);
+      kmax = M_PI * std::sqrt(s);
+    }
   }
   t.kmax = kmax;
   double nv[3], mv[3];
@@ -366,6 +386,7 @@ std::string build_tables(const ddi_params& p, HostTables& t, int* status) {
   for (int i = 0; i < 3; ++i) nv[i] = p.dip_n[i];
   if (nm > 0.0) for (int i = 0; i < 3; ++i) mv[i] = p.dip_m[i];
   else for (int i = 0; i < 3; ++i) mv[i] = nv[i];
+  for (int i = 0; i < 3; ++i) { t.nv[i] = nv[i]; t.mv[i] = mv[i]; }
 
   std::vector<double> tr, wr, tu, wu;
   gauss_legendre(static_cast<int>(p.n_rad), tr, wr);
@@ -426,7 +447,9 @@ std::string build_tables(const ddi_params& p, HostTables& t, int* status) {
         k_nat.push_back(k[0]);
         k_nat.push_back(k[1]);
         k_nat.push_back(k[2]);
-        c_nat.push_back(W * U * inv2pid);
+        // split: I_2 carries q(k) = exp(-|k|^2/s^2)
+        const double qk = t.split ? std::exp(-kk / (split_s * split_s)) : 1.0;
+        c_nat.push_back(W * U * inv2pid * qk);
       }
     }
   }

@@ -33,7 +33,8 @@ class DDIParams(ctypes.Structure):
                 ("dip_n", ctypes.c_double * 3), ("dip_m", ctypes.c_double * 3),
                 ("n_rad", ctypes.c_int64), ("n_pol", ctypes.c_int64), ("n_azi", ctypes.c_int64),
                 ("kmax", ctypes.c_double), ("nyquist_mask", ctypes.c_int32), ("tol", ctypes.c_double),
-                ("prec", ctypes.c_int32), ("kernel_width", ctypes.c_int32)]
+                ("prec", ctypes.c_int32), ("kernel_width", ctypes.c_int32),
+                ("split", ctypes.c_int32), ("split_s", ctypes.c_double)]
 
 
 class GPEParamsC(ctypes.Structure):
@@ -47,7 +48,8 @@ class PlanInfo(ctypes.Structure):
                 ("n_fine", ctypes.c_int64 * 3),
                 ("width", ctypes.c_int32), ("es_beta", ctypes.c_double), ("kmax", ctypes.c_double),
                 ("spread_items", ctypes.c_int64), ("spread_entries", ctypes.c_int64),
-                ("workspace_bytes", ctypes.c_int64)]
+                ("workspace_bytes", ctypes.c_int64),
+                ("split", ctypes.c_int32), ("split_s", ctypes.c_double)]
 
 
 EXPORTED = ["ddi_plan", "ddi_apply", "ddi_apply_adjoint", "ddi_type2", "ddi_type1", "gpe_energy_grad",
@@ -103,10 +105,13 @@ class DDIPlan:
     dip_n, dip_m     dipole axes (dip_m None means m = n).
     quad             (n_rad, n_pol, n_azi); n_pol ignored in 2D.
     prec             "fp64" or "mixed".
+    split, split_s   the split of Eq. 3.9 (3D): Phi = I_1 + I_2, I_1 by the zero-padded FFT,
+                     I_2 over the ball of radius kmax (quad and kmax are then I_2's;
+                     kmax = 0 and split_s = 0 select the defaults from tol and the box).
     """
 
     def __init__(self, dim, n, L, dip_n=(0.0, 0.0, 1.0), dip_m=None, quad=(32, 16, 32), kmax=0.0,
-                 nyquist_mask=True, tol=1e-13, prec="fp64", kernel_width=0):
+                 nyquist_mask=True, tol=1e-13, prec="fp64", kernel_width=0, split=False, split_s=0.0):
         if prec not in ("fp64", "mixed"):
             raise ValueError("prec must be 'fp64' or 'mixed'")
         p = DDIParams()
@@ -124,6 +129,8 @@ class DDIPlan:
         p.tol = float(tol)
         p.prec = DDI_MIXED if prec == "mixed" else DDI_FP64
         p.kernel_width = int(kernel_width)
+        p.split = 1 if split else 0
+        p.split_s = float(split_s)
         self.dim = int(dim)
         self.shape = tuple(int(v) for v in n[:dim])
         self.L = tuple(float(v) for v in L[:dim])
@@ -139,7 +146,8 @@ class DDIPlan:
                      "n_fine": tuple(info.n_fine),
                      "width": info.width, "es_beta": info.es_beta, "kmax": info.kmax,
                      "spread_items": info.spread_items, "spread_entries": info.spread_entries,
-                     "workspace_bytes": info.workspace_bytes}
+                     "workspace_bytes": info.workspace_bytes,
+                     "split": bool(info.split), "split_s": info.split_s}
         self.m_eff = int(info.m_eff)
 
     def __del__(self):

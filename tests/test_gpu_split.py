@@ -1,0 +1,166 @@
+"""The split of Eq. 3.9 (Phi = I_1 + I_2, 3D) on the HIP path, through the C ABI.
+
+Element by element against the oracle's split on the same seeded input: FP64 rel Linf
+<= 1e-12; mixed rel Linf <= 1e-6 against the FP64 oracle on the FP32-rounded input.  The
+partition parameter s and the ball radius of I_2 are recomputed by the oracle from the same
+reading, never taken from the plan.  At the benchmark's 128^3 size the result is checked, as
+the paper measures its errors, against the exact DDI of a contained Gaussian at sampled points.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import ddi_oracle as O
+from oracle import refs as R
+from paper_1504_02897_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1504_02897_amd.ddi import DDIError, DDIPlan  # noqa: E402
+
+DEV = "cuda:0"
+FP64_TOL = 1e-12
+MIXED_TOL = 1e-6
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def relinf(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / np.max(np.abs(np.asarray(b))))
+
+
+def to_dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dtype)
+
+
+def make_split(n, L, quad, dip_n, dip_m=None, prec="fp64", split_s=0.0, kmax=0.0):
+    tol = 1e-13 if prec == "fp64" else 1e-7
+    plan = DDIPlan(3, n, L, dip_n=dip_n, dip_m=dip_m, quad=quad, prec=prec, tol=tol, split=True,
+                   split_s=split_s, kmax=kmax)
+    s_o, r_o = O.split_defaults(L, tol)
+    s = split_s if split_s > 0 else s_o
+    R2 = kmax if kmax > 0 else s * math.sqrt(math.log(1.0 / tol))
+    assert plan.info["split"]
+    assert abs(plan.info["split_s"] - s) <= 1e-14 * s
+    assert abs(plan.info["kmax"] - R2) <= 1e-14 * R2
+    if split_s == 0 and kmax == 0:
+        assert abs(R2 - r_o) <= 1e-14 * r_o
+    prob = O.DDIProblem(dim=3, n=tuple(n), L=tuple(L), dip_n=tuple(dip_n),
+                        dip_m=None if dip_m is None else tuple(dip_m),
+                        n_rad=quad[0], n_pol=quad[1], n_azi=quad[2], kmax=R2)
+    return plan, prob, s
+
+
+CASES = [
+    # (n, L, quad, dip_n, dip_m, split_s, kmax, density)
+    ((32, 32, 32), (8.0, 8.0, 8.0), (16, 16, 32), (0.48, -0.6, 0.64), None, 0.0, 0.0, "c1"),
+    ((32, 32, 32), (8.0, 8.0, 8.0), (16, 16, 32), (0.0, 0.0, 1.0), None, 0.0, 0.0, "random"),
+    ((16, 32, 64), (6.0, 8.0, 10.0), (12, 8, 16), (0.6, 0.0, 0.8), (0.0, 0.8, 0.6), 0.7, 3.0, "random"),
+    ((64, 16, 16), (10.0, 5.0, 5.0), (8, 8, 8), (0.0, 1.0, 0.0), None, 0.0, 0.0, "random"),
+]
+
+
+def density(kind, n, L):
+    if kind == "c1":
+        return I.c1_density(n, L)
+    return I.random_field(11, n) ** 2
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "x".join(map(str, c[0])) + "_" + c[7])
+def test_split_fp64_matches_oracle(case):
+    n, L, quad, dn, dm, ss, km, kind = case
+    say(f"case: split fp64 n={n} L={L} quad={quad} s={ss} kmax={km} {kind}")
+    plan, prob, s = make_split(n, L, quad, dn, dm, split_s=ss, kmax=km)
+    rho = density(kind, n, L)
+    phi = plan.apply(to_dev(rho, torch.float64)).cpu().numpy()
+    ref = O.split_apply(rho, prob, s)
+    err = relinf(phi, ref)
+    say(f"  rel Linf {err:.3e}")
+    assert err <= FP64_TOL
+    # the short-range part is not negligible: I_2 alone differs from the total
+    i2 = O.split_long_range(rho, prob, s)
+    assert relinf(i2, ref) > 1e-3
+
+
+def test_split_adjoint_fp64():
+    """A^T of the split is the I_2 transpose plus I_1 (symmetric): equal to A in exact arithmetic."""
+    n, L = (32, 16, 32), (8.0, 6.0, 8.0)
+    say("case: split fp64 adjoint 32x16x32")
+    plan, prob, s = make_split(n, L, (12, 12, 24), (0.48, -0.6, 0.64), (0.0, 0.6, 0.8))
+    sig = I.random_field(3, n)
+    rho = I.random_field(4, n)
+    at = plan.apply_adjoint(to_dev(sig, torch.float64)).cpu().numpy()
+    k, c = O.split_long_range_nodes(prob, s)
+    sh = O.rhohat(sig, prob, k, sign=+1.0)                     # the literal transpose of I_2
+    ref = O.split_short_range(sig, prob, s) + O.nodes_to_grid(c * sh, prob, k, sign=-1.0, real=True)
+    assert relinf(at, ref) <= FP64_TOL
+    a = plan.apply(to_dev(rho, torch.float64)).cpu().numpy()
+    lhs, rhs = float(np.sum(sig * a)), float(np.sum(at * rho))
+    assert abs(lhs - rhs) <= 1e-12 * float(np.sum(np.abs(sig * a)))
+
+
+def test_split_mixed_matches_oracle():
+    n, L = (32, 32, 32), (8.0, 8.0, 8.0)
+    say("case: split mixed 32^3 c1")
+    plan, prob, s = make_split(n, L, (12, 12, 24), (0.48, -0.6, 0.64), prec="mixed")
+    rho32 = I.c1_density(n, L).astype(np.float32)
+    phi = plan.apply(to_dev(rho32, torch.float32)).cpu().numpy().astype(np.float64)
+    ref = O.split_apply(rho32.astype(np.float64), prob, s)
+    err = relinf(phi, ref)
+    say(f"  rel Linf {err:.3e}")
+    assert err <= MIXED_TOL
+
+
+def test_split_128_matches_exact_gaussian_ddi():
+    """At the benchmark's size (128^3 on [-12, 12)^3, I_2 on a 32 x 32 x 64 ball) against the exact
+    DDI of an axis-aligned Gaussian (Ex. 2.3), contained in the box and resolved by the grid."""
+    n, L = (128, 128, 128), (12.0, 12.0, 12.0)
+    a = np.array([0.5, 0.5, 0.8])
+    c = np.array([0.3, -0.2, 0.1])
+    dn = (0.3, 0.4, math.sqrt(0.75))
+    say("case: split fp64 128^3 vs exact Gaussian DDI")
+    plan, prob, s = make_split(n, L, (32, 32, 64), dn)
+    xs = I.grid_axes(n, L)
+    X = np.meshgrid(*xs, indexing="ij")
+    rho = np.prod([R.heat_kernel(a[i], X[i] - c[i]) for i in range(3)], axis=0)
+    phi = plan.apply(to_dev(rho, torch.float64)).cpu().numpy()
+    rng = np.random.default_rng(9)
+    pts = np.concatenate([rng.integers(0, 128, size=(16, 3)),
+                          np.array([[0, 0, 0], [127, 127, 127], [64, 64, 64], [64, 70, 60]])])
+    ex = np.array([R.phi_gaussian_product([xs[0][p[0]], xs[1][p[1]], xs[2][p[2]]], a, c, dn) for p in pts])
+    got = np.array([phi[tuple(p)] for p in pts])
+    err = float(np.max(np.abs(got - ex)) / np.max(np.abs(ex)))
+    say(f"  sampled rel Linf vs exact {err:.3e}; M_eff {plan.info['m_eff']}")
+    assert err < 1e-11
+
+
+def test_split_rejected_in_2d():
+    with pytest.raises(DDIError):
+        DDIPlan(2, (64, 64), (8.0, 8.0), quad=(16, 1, 32), split=True)
+
+
+def test_split_c2_mixture_matches_exact_ddi():
+    """The benchmark's split configuration on the c2_128 input (|psi|^2 of four seeded lumps, which
+    expands into Gaussian products, Ex. 2.3) against the exact DDI at sampled points."""
+    wl = I.WORKLOADS["c2_128"]
+    d = I.mixture_workload("c2_128", seed=0)
+    say("case: split fp64 c2_128 input vs exact mixture DDI")
+    plan, prob, s = make_split(wl["n"], wl["L"], (32, 32, 64), tuple(d["dip_n"]))
+    phi = plan.apply(to_dev(d["rho"], torch.float64)).cpu().numpy()
+    prods = R.gaussian_lumps_to_products(d["lumps"], d["scale"])
+    xs = I.grid_axes(wl["n"], wl["L"])
+    rng = np.random.default_rng(1)
+    pts = np.concatenate([rng.integers(0, 128, size=(14, 3)),
+                          np.array([[0, 0, 0], [127, 127, 127], [64, 64, 64], [3, 76, 3], [64, 20, 110]])])
+    ex = np.array([R.phi_mixture([xs[0][p[0]], xs[1][p[1]], xs[2][p[2]]], prods, d["dip_n"]) for p in pts])
+    got = np.array([phi[tuple(p)] for p in pts])
+    err = float(np.max(np.abs(got - ex)))
+    say(f"  sampled max abs err {err:.3e}, max|Phi| {np.max(np.abs(phi)):.6e}")
+    assert err < 1e-10 * np.max(np.abs(phi))

@@ -50,7 +50,8 @@ class Params(ctypes.Structure):
                 ("dip_n", ctypes.c_double * 3), ("dip_m", ctypes.c_double * 3),
                 ("n_rad", ctypes.c_int64), ("n_pol", ctypes.c_int64), ("n_azi", ctypes.c_int64),
                 ("kmax", ctypes.c_double), ("nyquist_mask", ctypes.c_int32), ("tol", ctypes.c_double),
-                ("prec", ctypes.c_int32), ("kernel_width", ctypes.c_int32)]
+                ("prec", ctypes.c_int32), ("kernel_width", ctypes.c_int32),
+                ("split", ctypes.c_int32), ("split_s", ctypes.c_double)]
 
 
 def _params(**kw):
@@ -67,6 +68,8 @@ def _params(**kw):
     p.tol = kw.get("tol", 1e-13)
     p.prec = kw.get("prec", 0)
     p.kernel_width = kw.get("kernel_width", 0)
+    p.split = kw.get("split", 0)
+    p.split_s = kw.get("split_s", 0.0)
     return p
 
 
@@ -81,6 +84,9 @@ def _params(**kw):
     (dict(tol=0.0), 1),
     (dict(kernel_width=17), 1),
     (dict(prec=7), 1),
+    (dict(split=2), 1),
+    (dict(split=1, split_s=float("inf")), 1),
+    (dict(split=1, dim=2, n=(64, 64)), 4),    # the split is built for 3D only
 ])
 def test_invalid_plans_are_rejected_before_device_use(lib, bad, code):
     lib.ddi_plan.argtypes = [ctypes.POINTER(Params), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
