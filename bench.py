@@ -196,7 +196,7 @@ def other_workloads(args, torch, np, I, DDIPlan):
              "diff_vs": "rel Linf difference from the full-ball FP64 apply (quadrature 96x48x96) on the same "
                         "input; it is the full-ball quadrature's own error on this wide mixture (the split is "
                         "within 1e-10 of max|Phi| of the exact mixture DDI at sampled points)"}
-    for prec, quad, tol in (("fp64", (32, 32, 64), wl["tol"]), ("mixed", (24, 24, 48), 1e-7)):
+    for prec, quad, tol in (("fp64", (32, 32, 64), wl["tol"]), ("mixed", (16, 16, 32), 1e-7)):
         p = DDIPlan(3, wl["n"], wl["L"], dip_n=tuple(d["dip_n"]), quad=quad, tol=tol, prec=prec, split=True)
         rr = r if prec == "fp64" else r.float()
         o = torch.empty_like(rr)

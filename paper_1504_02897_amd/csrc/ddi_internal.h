@@ -121,6 +121,10 @@ struct Schedule {
   // this schedule read and write only the window, and the spread writes only its tiles.
   int32_t z0 = 0;
   int32_t nz = 0;
+  // Axis-1 window (3D): every scheduled support lies at signed fine positions [-ny/2, ny/2) on
+  // axis 1 (ny even; n_fine[1] when the supports reach the whole axis).  The axis-0 passes
+  // transform only those lines and the axis-1 passes write (type-2) or read (type-1) only them.
+  int32_t ny = 0;
 };
 
 // The two node subsets a plan schedules.  kAll: every node (the type-2 / type-1 entry

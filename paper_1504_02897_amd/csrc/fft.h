@@ -23,13 +23,14 @@ struct SplitSymbol {
 
 // In-place transforms of length n along axis 0 or 1 of a [d0][d1][d2] complex
 // array.  The other non-last axis runs over n_o lines (the compact modes of an
-// oversampled axis when o_compact); in_c / out_c: only the nc active positions
-// of each line are read / written (exp(SIGN 2 pi i jk/n)).  Only the lines at
-// last-axis positions [z0, z0 + nz) (mod d2) are transformed: z0 and nz are
-// multiples of 8, or z0 = 0 and nz = d2.
+// oversampled axis when o_compact); in_c: only the nc active positions of each
+// line are read (the rest taken as zero); out_c: only the nc_out active positions
+// are written (exp(SIGN 2 pi i jk/n)).  Only the lines at last-axis positions
+// [z0, z0 + nz) (mod d2) are transformed: z0 and nz are multiples of 8, or z0 = 0
+// and nz = d2.
 template <typename T, int SIGN>
 hipError_t launch_strided(int n, Complex<T>* F, int axis, int d0, int d1, int d2, int n_o, int o_compact, int nc,
-                          int in_c, int out_c, int z0, int nz, const Complex<T>* tw, hipStream_t s);
+                          int in_c, int out_c, int nc_out, int z0, int nz, const Complex<T>* tw, hipStream_t s);
 
 // Transforms of length n along the last axis; lines run over the n0 x n1 compact
 // grid (R2C_PAD, C2R_TRUNC: mapped into a [d0][d1][n] oversampled array) or over

@@ -208,11 +208,11 @@ __device__ __forceinline__ int cmap(int k, int n, int nc) { return k < nc - nc /
 // Lines along axis `axis` (0 or 1) of a [d0][d1][d2] complex array, B consecutive
 // z per workgroup.  The other non-z axis runs over n_o lines (compact when
 // o_compact: index o -> fine index fmap(o, d_o, n_o)).  in_compact / out_compact:
-// only the N_c active positions of the line are read (rest zero) / written.
+// only the nc_axis / nc_out active positions of the line are read (rest zero) / written.
 template <typename T, int N, int SIGN, int MAXT>
 __global__ void __launch_bounds__(MAXT) k_fft_strided(C<T>* __restrict__ F, int axis, int d0, int d1, int d2,
                                                      int n_o, int o_compact, int nc_axis, int in_compact,
-                                                     int out_compact, int z0, int nzb,
+                                                     int out_compact, int nc_out, int z0, int nzb,
                                                      const C<T>* __restrict__ tw, int B) {
   extern __shared__ unsigned char smem_raw[];
   LdsElem<T, N>* lds = reinterpret_cast<LdsElem<T, N>*>(smem_raw);
@@ -240,18 +240,18 @@ __global__ void __launch_bounds__(MAXT) k_fft_strided(C<T>* __restrict__ F, int 
 #pragma unroll
   for (int i = 0; i < P::R1; ++i) {
     const int k = LineOut<P, N>::k(j0, i);
-    if (!out_compact || active(k, N, nc_axis)) F[base + k * stride] = v[i];
+    if (!out_compact || active(k, N, nc_out)) F[base + k * stride] = v[i];
   }
 }
 
 // ------------------------------------------------------------------ split: axis-0 pass with the symbol
 // Moves a line from the output distribution of line_fft (thread j0 holds k = LineOut::k(j0, i)
-// in v[i]) to its input distribution (v[r] = x[j0 + r*TL]) through LDS.  Ends with a barrier,
-// so the next line_fft may write LDS at once.
+// in v[i]) to its input distribution (v[r] = x[j0 + r*TL]) through LDS, in place: every value of
+// a component is stored before any is read back, so no second array is held.  Ends with a
+// barrier, so the next line_fft may write LDS at once.
 template <typename T, int N, typename P, typename Addr>
 __device__ __forceinline__ void line_to_natural(LdsElem<T, N>* lds, Addr addr, int j0, C<T>* v) {
   constexpr int TL = N / P::R1;
-  C<T> w[P::R1];
   if constexpr (SplitExchange<T, N>::value) {
 #pragma unroll
     for (int part = 0; part < 2; ++part) {
@@ -262,8 +262,8 @@ __device__ __forceinline__ void line_to_natural(LdsElem<T, N>* lds, Addr addr, i
 #pragma unroll
       for (int r = 0; r < P::R1; ++r) {
         const T x = lds[addr(j0 + r * TL)];
-        if (part == 0) w[r].re = x;
-        else w[r].im = x;
+        if (part == 0) v[r].re = x;
+        else v[r].im = x;
       }
     }
   } else {
@@ -272,21 +272,26 @@ __device__ __forceinline__ void line_to_natural(LdsElem<T, N>* lds, Addr addr, i
     for (int i = 0; i < P::R1; ++i) lds[addr(LineOut<P, N>::k(j0, i))] = v[i];
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < P::R1; ++r) w[r] = lds[addr(j0 + r * TL)];
+    for (int r = 0; r < P::R1; ++r) v[r] = lds[addr(j0 + r * TL)];
   }
   __syncthreads();
-#pragma unroll
-  for (int r = 0; r < P::R1; ++r) v[r] = w[r];
 }
+
+// Radices of the symbol pass: eight values per thread from 128 points up, so that two
+// transforms, the symbol and the exchange fit in 128 VGPRs (four waves per SIMD; with sixteen
+// FP64 values per thread the kernel spills or runs one wave per SIMD).
+template <int N> struct SymbolRadix : RadixPlan<N> {};
+template <> struct SymbolRadix<128> { static constexpr int R1 = 8, R2 = 4, R3 = 4; };
+template <> struct SymbolRadix<256> { static constexpr int R1 = 8, R2 = 8, R3 = 4; };
 
 // Lines (., y, z) of the padded spectrum for y in [0, d1) and z in [0, nz); B consecutive z per
 // workgroup.  See launch_symbol.
 template <typename T, int N, int MAXT>
-__global__ void __launch_bounds__(MAXT) k_fft_symbol(C<T>* __restrict__ F, int d1, int d2, int nc_axis, int nzb,
+__global__ void __launch_bounds__(MAXT, 1024 / MAXT) k_fft_symbol(C<T>* __restrict__ F, int d1, int d2, int nc_axis, int nzb,
                                                     SplitSymbol sp, const C<T>* __restrict__ tw, int B) {
   extern __shared__ unsigned char smem_raw[];
   LdsElem<T, N>* lds = reinterpret_cast<LdsElem<T, N>*>(smem_raw);
-  using P = Radix<T, N, false>;
+  using P = SymbolRadix<N>;
   constexpr int TL = N / P::R1;
   const int b = threadIdx.x % B;
   const int j0 = threadIdx.x / B;
@@ -295,13 +300,8 @@ __global__ void __launch_bounds__(MAXT) k_fft_symbol(C<T>* __restrict__ F, int d
   const int64_t base = static_cast<int64_t>(y) * d2 + z;
   const int64_t stride = static_cast<int64_t>(d1) * d2;
   auto addr = [B, b](int k) { return k * B + b; };
-  C<T> v[P::R1];
-#pragma unroll
-  for (int r = 0; r < P::R1; ++r) {
-    const int k = j0 + r * TL;
-    v[r] = active(k, N, nc_axis) ? F[base + k * stride] : C<T>{0, 0};
-  }
-  line_fft<T, N, -1, P>(lds, addr, j0, tw, v);
+  // the multiplier of each output mode this thread will hold, evaluated before the line is
+  // loaded (the transcendental work then does not overlap the transform's live values)
   // modes: m1 signed from y (Nyquist plane y = d1/2 dropped); m2 = z in [0, d2/2)
   const bool nyq1 = 2 * y == d1;
   const double k1 = (y < d1 / 2 ? y : y - d1) * sp.dk[1];
@@ -310,19 +310,29 @@ __global__ void __launch_bounds__(MAXT) k_fft_symbol(C<T>* __restrict__ F, int d
   const double kn12 = k1 * sp.n[1] + k2 * sp.n[2];
   const double km12 = k1 * sp.m[1] + k2 * sp.m[2];
   const double u12 = k1 * k1 + k2 * k2;
+  double mult[P::R1];
 #pragma unroll
   for (int i = 0; i < P::R1; ++i) {
     const int k = LineOut<P, N>::k(j0, i);
     const double k0 = (k < N / 2 ? k : k - N) * sp.dk[0];
     const double u = k0 * k0 + u12;
-    double mult = 0.0;
+    mult[i] = 0.0;
     if (!nyq1 && 2 * k != N && u > 0.0) {
       const double kn = k0 * sp.n[0] + kn12;
       const double km = k0 * sp.m[0] + km12;
-      mult = -expm1(-u * sp.inv_s2) * (3.0 * kn * km / u - sp.nm) * w2;
+      mult[i] = -expm1(-u * sp.inv_s2) * (3.0 * kn * km / u - sp.nm) * w2;
     }
-    v[i] = C<T>{static_cast<T>(v[i].re * mult), static_cast<T>(v[i].im * mult)};
   }
+  C<T> v[P::R1];
+#pragma unroll
+  for (int r = 0; r < P::R1; ++r) {
+    const int k = j0 + r * TL;
+    v[r] = active(k, N, nc_axis) ? F[base + k * stride] : C<T>{0, 0};
+  }
+  line_fft<T, N, -1, P>(lds, addr, j0, tw, v);
+#pragma unroll
+  for (int i = 0; i < P::R1; ++i)
+    v[i] = C<T>{static_cast<T>(v[i].re * mult[i]), static_cast<T>(v[i].im * mult[i])};
   line_to_natural<T, N, P>(lds, addr, j0, v);
   line_fft<T, N, 1, P>(lds, addr, j0, tw, v);
 #pragma unroll
@@ -418,7 +428,7 @@ __global__ void __launch_bounds__(256) k_fft_contig(const void* in, void* out,
 // ------------------------------------------------------------------ dispatch
 template <typename T, int N, int SIGN>
 static hipError_t launch_strided_n(C<T>* F, int axis, int d0, int d1, int d2, int n_o, int o_compact, int nc,
-                                   int in_c, int out_c, int z0, int nz, const C<T>* tw, hipStream_t s) {
+                                   int in_c, int out_c, int nc_out, int z0, int nz, const C<T>* tw, hipStream_t s) {
   constexpr int TL = N / Radix<T, N, false>::R1;
   // lines per workgroup: at least 256 threads, and row segments of >= 128 B along the
   // contiguous axis (coalescing) as far as 1024 threads and 64 KB of LDS allow; a window
@@ -430,31 +440,33 @@ static hipError_t launch_strided_n(C<T>* F, int axis, int d0, int d1, int d2, in
   while (B > d2) B >>= 1;
   while (B > 1 && (z0 % B != 0 || nz % B != 0)) B >>= 1;
   if (z0 % B != 0 || nz % B != 0 || nz > d2 || z0 < 0 || z0 >= d2) return hipErrorInvalidValue;
+  if (n_o < 0 || n_o > (axis == 0 ? d1 : d0) || nc < 0 || nc > N || nc_out < 0 || nc_out > N)
+    return hipErrorInvalidValue;
   const size_t shm = static_cast<size_t>(B) * N * sizeof(LdsElem<T, N>);
   const int nzb = nz / B;
   const int blocks = n_o * nzb;
   if (blocks == 0) return hipSuccess;
   if (B * TL <= 256)
     hipLaunchKernelGGL((k_fft_strided<T, N, SIGN, 256>), dim3(blocks), dim3(B * TL), shm, s, F, axis, d0, d1, d2,
-                       n_o, o_compact, nc, in_c, out_c, z0, nzb, tw, B);
+                       n_o, o_compact, nc, in_c, out_c, nc_out, z0, nzb, tw, B);
   else
     hipLaunchKernelGGL((k_fft_strided<T, N, SIGN, 1024>), dim3(blocks), dim3(B * TL), shm, s, F, axis, d0, d1, d2,
-                       n_o, o_compact, nc, in_c, out_c, z0, nzb, tw, B);
+                       n_o, o_compact, nc, in_c, out_c, nc_out, z0, nzb, tw, B);
   return hipGetLastError();
 }
 
 template <typename T, int SIGN>
 hipError_t launch_strided(int n, C<T>* F, int axis, int d0, int d1, int d2, int n_o, int o_compact, int nc,
-                                 int in_c, int out_c, int z0, int nz, const C<T>* tw, hipStream_t s) {
+                                 int in_c, int out_c, int nc_out, int z0, int nz, const C<T>* tw, hipStream_t s) {
   switch (n) {
-    case 8: return launch_strided_n<T, 8, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, z0, nz, tw, s);
-    case 16: return launch_strided_n<T, 16, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, z0, nz, tw, s);
-    case 32: return launch_strided_n<T, 32, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, z0, nz, tw, s);
-    case 64: return launch_strided_n<T, 64, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, z0, nz, tw, s);
-    case 128: return launch_strided_n<T, 128, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, z0, nz, tw, s);
-    case 256: return launch_strided_n<T, 256, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, z0, nz, tw, s);
-    case 512: return launch_strided_n<T, 512, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, z0, nz, tw, s);
-    case 1024: return launch_strided_n<T, 1024, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, z0, nz, tw, s);
+    case 8: return launch_strided_n<T, 8, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, nc_out, z0, nz, tw, s);
+    case 16: return launch_strided_n<T, 16, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, nc_out, z0, nz, tw, s);
+    case 32: return launch_strided_n<T, 32, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, nc_out, z0, nz, tw, s);
+    case 64: return launch_strided_n<T, 64, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, nc_out, z0, nz, tw, s);
+    case 128: return launch_strided_n<T, 128, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, nc_out, z0, nz, tw, s);
+    case 256: return launch_strided_n<T, 256, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, nc_out, z0, nz, tw, s);
+    case 512: return launch_strided_n<T, 512, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, nc_out, z0, nz, tw, s);
+    case 1024: return launch_strided_n<T, 1024, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, nc_out, z0, nz, tw, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -462,7 +474,7 @@ hipError_t launch_strided(int n, C<T>* F, int axis, int d0, int d1, int d2, int 
 template <typename T, int N>
 static hipError_t launch_symbol_n(C<T>* F, int d1, int d2, int nc, int nz, const SplitSymbol& sp, const C<T>* tw,
                                   hipStream_t s) {
-  constexpr int TL = N / Radix<T, N, false>::R1;
+  constexpr int TL = N / SymbolRadix<N>::R1;
   int B = 256 / TL;   // as in the strided pass: >= 128-byte row segments where LDS allows
   while (B * static_cast<int>(sizeof(C<T>)) < 128 && 2 * B * TL <= 1024 &&
          static_cast<size_t>(2 * B) * N * sizeof(LdsElem<T, N>) <= 65536)
@@ -529,7 +541,7 @@ hipError_t launch_contig(int n, const void* in, void* out, int n0, int n1, int d
 }
 
 #define DDI_INST_STRIDED(T, S)                                                                                  \
-  template hipError_t launch_strided<T, S>(int, C<T>*, int, int, int, int, int, int, int, int, int, int, int,    \
+  template hipError_t launch_strided<T, S>(int, C<T>*, int, int, int, int, int, int, int, int, int, int, int, int, \
                                            const C<T>*, hipStream_t);
 #define DDI_INST_CONTIG(T, S, M)                                                                                \
   template hipError_t launch_contig<T, S, M>(int, const void*, void*, int, int, int, int, int, int, int,        \

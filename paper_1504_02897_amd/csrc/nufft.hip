@@ -692,22 +692,37 @@ __global__ void __launch_bounds__(256) k_interp_gather(const C<double>* __restri
   out[q] = C<T>{static_cast<T>(s * sr), static_cast<T>(s * si)};
 }
 
-// Sum the partial tiles of each split tile in slot order (deterministic); one thread per point.
+// Sum the partial tiles of each split tile in slot order (deterministic); one thread per point,
+// kReduceSplit workgroups per tile (a hot tile's hundred slots are then read by several CUs).
+constexpr int kReduceSplit = 4;
 template <typename T, int TX, int TY>
-__global__ void __launch_bounds__(64 * kTileZ) k_spread_reduce(C<T>* __restrict__ F,
+__global__ void __launch_bounds__(64 * kTileZ / kReduceSplit) k_spread_reduce(C<T>* __restrict__ F,
                                                                const C<T>* __restrict__ partial,
                                                                const ReduceItem* __restrict__ red, int nf1, int nf2,
                                                                int nt1, int nt2) {
-  const int lane = threadIdx.x & 63;
-  const int i = threadIdx.x >> 6;
-  const ReduceItem r = red[blockIdx.x];
+  const int pt = (blockIdx.x % kReduceSplit) * (64 * kTileZ / kReduceSplit) + threadIdx.x;   // point of the tile
+  const int lane = pt & 63;
+  const int i = pt >> 6;
+  const ReduceItem r = red[blockIdx.x / kReduceSplit];
   const int tz = r.tile % nt2;
   const int ty = (r.tile / nt2) % nt1;
   const int tx = r.tile / (nt2 * nt1);
   const int x = tx * TX + lane / TY, y = ty * TY + lane % TY, z = tz * kTileZ + i;
   const C<T>* src = partial + (static_cast<int64_t>(r.first_slot) * kTileZ + i) * 64 + lane;
+  // sixteen loads in flight (hot tiles of a small ball of nodes have a hundred slots and more);
+  // the sum stays in slot order
   double sr = 0.0, si = 0.0;
   int s = 0;
+  for (; s + 16 <= r.nslots; s += 16) {
+    C<T> v[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) v[j] = src[static_cast<int64_t>(s + j) * 64 * kTileZ];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      sr += static_cast<double>(v[j].re);
+      si += static_cast<double>(v[j].im);
+    }
+  }
   for (; s + 4 <= r.nslots; s += 4) {
     C<T> v[4];
 #pragma unroll
@@ -753,17 +768,19 @@ template <typename T, int SIGN>
 static hipError_t type2_fft(DevicePlan& P, int which, const T* rho, hipStream_t s, hipEvent_t* ev) {
   const HostTables& H = P.H;
   const int z0 = H.sched[which].z0, nz = H.sched[which].nz;   // only the window is needed
+  const int ny = H.sched[which].ny;                               // and on axis 1 only its lines
+  const int ycut = ny < H.nf[1];
   C<T>* F = reinterpret_cast<C<T>*>(P.fine);
   const C<T>* tw2 = reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[2])]);
   DDI_CHECK((launch_contig<T, SIGN, R2C_PAD>(H.nf[2], rho, F, H.N[0], H.N[1], H.nf[0], H.nf[1], H.N[2], z0, nz,
                                              P.deconv[0], P.deconv[1], P.deconv[2], tw2, s)));
   DDI_REC(1);
-  DDI_CHECK((launch_strided<T, SIGN>(H.nf[1], F, 1, H.nf[0], H.nf[1], H.nf[2], H.N[0], 1, H.N[1], 1, 0, z0, nz,
-                                     reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[1])]), s)));
+  DDI_CHECK((launch_strided<T, SIGN>(H.nf[1], F, 1, H.nf[0], H.nf[1], H.nf[2], H.N[0], 1, H.N[1], 1, ycut, ny, z0,
+                                     nz, reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[1])]), s)));
   DDI_REC(2);
   if (H.nf[0] > 1) {
-    DDI_CHECK((launch_strided<T, SIGN>(H.nf[0], F, 0, H.nf[0], H.nf[1], H.nf[2], H.nf[1], 0, H.N[0], 1, 0, z0, nz,
-                                       reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[0])]), s)));
+    DDI_CHECK((launch_strided<T, SIGN>(H.nf[0], F, 0, H.nf[0], H.nf[1], H.nf[2], ny, ycut, H.N[0], 1, 0, H.N[0], z0,
+                                       nz, reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[0])]), s)));
   }
   DDI_REC(3);
   return hipSuccess;
@@ -774,14 +791,16 @@ template <typename T, int SIGN>
 static hipError_t type1_fft(DevicePlan& P, int which, T* phi, hipStream_t s, hipEvent_t* ev) {
   const HostTables& H = P.H;
   const int z0 = H.sched[which].z0, nz = H.sched[which].nz;   // the spread filled only the window
+  const int ny = H.sched[which].ny;                               // and on axis 1 only its lines
+  const int ycut = ny < H.nf[1];
   C<T>* F = reinterpret_cast<C<T>*>(P.fine);
   if (H.nf[0] > 1) {
-    DDI_CHECK((launch_strided<T, SIGN>(H.nf[0], F, 0, H.nf[0], H.nf[1], H.nf[2], H.nf[1], 0, H.N[0], 0, 1, z0, nz,
-                                       reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[0])]), s)));
+    DDI_CHECK((launch_strided<T, SIGN>(H.nf[0], F, 0, H.nf[0], H.nf[1], H.nf[2], ny, ycut, H.N[0], 0, 1, H.N[0], z0,
+                                       nz, reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[0])]), s)));
   }
   DDI_REC(7);
-  DDI_CHECK((launch_strided<T, SIGN>(H.nf[1], F, 1, H.nf[0], H.nf[1], H.nf[2], H.N[0], 1, H.N[1], 0, 1, z0, nz,
-                                     reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[1])]), s)));
+  DDI_CHECK((launch_strided<T, SIGN>(H.nf[1], F, 1, H.nf[0], H.nf[1], H.nf[2], H.N[0], 1, ny, ycut, 1, H.N[1], z0,
+                                     nz, reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[1])]), s)));
   DDI_REC(8);
   const C<T>* tw2 = reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[2])]);
   DDI_CHECK((launch_contig<T, SIGN, C2R_TRUNC>(H.nf[2], F, phi, H.N[0], H.N[1], H.nf[0], H.nf[1], H.N[2], z0, nz,
@@ -910,7 +929,8 @@ static hipError_t spread_t(DevicePlan& P, int which, const C<T>* g, hipStream_t 
   DDI_CHECK(hipGetLastError());
   DDI_REC(5);
   if (!S.reduces.empty()) {
-    hipLaunchKernelGGL((k_spread_reduce<T, TX, TY>), dim3(static_cast<int>(S.reduces.size())), dim3(64 * kTileZ), 0,
+    hipLaunchKernelGGL((k_spread_reduce<T, TX, TY>), dim3(static_cast<int>(S.reduces.size()) * kReduceSplit),
+                       dim3(64 * kTileZ / kReduceSplit), 0,
                        s, F, reinterpret_cast<const C<T>*>(P.partial), D.reduces, H.nf[1], H.nf[2], H.ntiles[1],
                        H.ntiles[2]);
     DDI_CHECK(hipGetLastError());
@@ -982,9 +1002,11 @@ hipError_t run_split_short(DevicePlan& P, const T* rho, T* phi, hipStream_t s) {
   sp.scale = 1.0 / (static_cast<double>(H.nf[0]) * H.nf[1] * H.nf[2]);
   DDI_CHECK((launch_contig<T, -1, R2C_PAD>(H.nf[2], rho, F, H.N[0], H.N[1], H.nf[0], H.nf[1], H.N[2], 0, nz, P.ones,
                                            P.ones, P.ones, tw2, s)));
-  DDI_CHECK((launch_strided<T, -1>(H.nf[1], F, 1, H.nf[0], H.nf[1], H.nf[2], H.N[0], 1, H.N[1], 1, 0, 0, nz, tw1, s)));
+  DDI_CHECK((launch_strided<T, -1>(H.nf[1], F, 1, H.nf[0], H.nf[1], H.nf[2], H.N[0], 1, H.N[1], 1, 0, H.N[1], 0, nz,
+                                   tw1, s)));
   DDI_CHECK((launch_symbol<T>(H.nf[0], F, H.nf[1], H.nf[2], H.N[0], nz, sp, tw0, s)));
-  DDI_CHECK((launch_strided<T, 1>(H.nf[1], F, 1, H.nf[0], H.nf[1], H.nf[2], H.N[0], 1, H.N[1], 0, 1, 0, nz, tw1, s)));
+  DDI_CHECK((launch_strided<T, 1>(H.nf[1], F, 1, H.nf[0], H.nf[1], H.nf[2], H.N[0], 1, H.N[1], 0, 1, H.N[1], 0, nz,
+                                  tw1, s)));
   DDI_CHECK((launch_contig<T, 1, C2R_ADD>(H.nf[2], F, phi, H.N[0], H.N[1], H.nf[0], H.nf[1], H.N[2], 0, nz, P.ones,
                                           P.ones, P.ones, tw2, s)));
   return hipSuccess;

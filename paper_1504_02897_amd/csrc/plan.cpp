@@ -196,6 +196,27 @@ std::string build_spread_schedule(const HostTables& t, const std::vector<int64_t
       }
     }
   }
+  // axis-1 window, centred on mode 0 (3D only): the smallest ny with every support inside the
+  // signed positions [-ny/2, ny/2) and ny/2 a multiple of the tile extent, so that a tile lies
+  // wholly inside or outside (the matrix-core interpolation multiplies whole tiles, and rows
+  // outside the window are never transformed)
+  {
+    const int n = t.nf[1];
+    S.ny = n;
+    if (t.dim == 3) {
+      int need = 2;
+      for (int64_t s = 0; s < M; ++s) {
+        if (!used(s)) continue;
+        for (int i = 0; i < t.W[1]; ++i) {
+          const int pos = (t.l0[3 * s + 1] + i) % n;
+          const int sp = pos < n / 2 ? pos : pos - n;
+          need = std::max(need, sp >= 0 ? 2 * (sp + 1) : -2 * sp);
+        }
+      }
+      const int half = (need / 2 + t.tile[1] - 1) / t.tile[1] * t.tile[1];
+      S.ny = std::min(n, 2 * half);
+    }
+  }
   auto in_window = [&](int z) { return ((z - S.z0) % t.nf[2] + t.nf[2]) % t.nf[2] < S.nz; };
   std::vector<int64_t> count(ntile_total + 1, 0);
   int tx[kWMax], ty[kWMax], tz[kWMax];
@@ -219,7 +240,14 @@ std::string build_spread_schedule(const HostTables& t, const std::vector<int64_t
           }
     }
   }
-  const int chunk = t.row_windows && kSpreadMfma ? kSpreadChunkMfma : kSpreadChunk;
+  // chunk length of the matrix-core kernels: the tuned maximum, or shorter when the entries
+  // would otherwise fill fewer items than the 4096 waves the spread keeps resident (a small
+  // ball of nodes crowds a few tiles, and one wave per long chunk then sets the duration)
+  int chunk = kSpreadChunk;
+  if (t.row_windows && kSpreadMfma) {
+    const int64_t per_wave = (count[ntile_total] + 4095) / 4096;
+    chunk = static_cast<int>(std::min<int64_t>(kSpreadChunkMfma, std::max<int64_t>(32, (per_wave + 15) / 16 * 16)));
+  }
   S.items.clear();
   S.reduces.clear();
   int32_t slot = 0;
