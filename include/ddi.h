@@ -154,7 +154,10 @@ typedef struct {
 ddi_status ddi_plan(const ddi_params* params, void* stream, ddi_plan_t* out);
 
 /* Phi = A rho (Sec. 2.1, Eqs. DDI-Con, DDI-Trun1).  rho_dev, phi_dev: real grids.
- * A split plan returns I_1 + I_2 (Eq. 3.9): the I_2 quadrature sum, then I_1 added to it. */
+ * A split plan returns I_1 + I_2 (Eq. 3.9): I_1 is computed on a stream the plan owns (default
+ * priority), forked from `stream` by an event, concurrently with I_2 on `stream`, and added to
+ * phi after I_2; `stream` waits for it before any later work, so the call is ordered on
+ * `stream` like every other. */
 ddi_status ddi_apply(ddi_plan_t plan, const void* rho_dev, void* phi_dev, void* stream);
 
 /* rhobar = A^T phibar, executed literally: transform with exp(+i k.x) to the

@@ -44,7 +44,11 @@ hipError_t upload(X** dst, const X* src, size_t count, hipStream_t s, int64_t& b
 }
 
 void free_plan(ddi::DevicePlan& P) {
-  void* ptrs[] = {P.nodes, P.c_scaled, P.c_half, P.ones, P.deconv[0], P.deconv[1], P.deconv[2],
+  if (P.aux) (void)hipStreamSynchronize(P.aux);
+  for (hipEvent_t e : {P.ev_fork, P.ev_long, P.ev_join})
+    if (e) (void)hipEventDestroy(e);
+  if (P.aux) (void)hipStreamDestroy(P.aux);
+  void* ptrs[] = {P.nodes, P.c_scaled, P.c_half, P.ones, P.fine_short, P.deconv[0], P.deconv[1], P.deconv[2],
                   P.fine, P.gnodes, P.partial, P.ipartial, P.pads, P.gpe_rho, P.gpe_phi, P.gpe_phit, P.gpe_c1, P.gpe_c2, P.gpe_red};
   for (auto& d : P.dsched) {
     void* sp[] = {d.list, d.items, d.reduces, d.interp_items, d.interp_direct, d.gptr, d.gpos, d.ent};
@@ -132,6 +136,15 @@ ddi_status build_device(ddi::DevicePlan& P, hipStream_t s, std::vector<ddi::Node
   const int64_t nfine = static_cast<int64_t>(H.nf[0]) * H.nf[1] * H.nf[2];
   HIP_TRY(hipMalloc(&P.fine, nfine * sizeof(ddi::Complex<T>)), "allocate fine grid");
   bytes += nfine * static_cast<int64_t>(sizeof(ddi::Complex<T>));
+  if (H.split) {
+    // I_1 of the split runs beside I_2: its own padded grid, stream (default priority) and events
+    HIP_TRY(hipMalloc(&P.fine_short, nfine * sizeof(ddi::Complex<T>)), "allocate the split's padded grid");
+    bytes += nfine * static_cast<int64_t>(sizeof(ddi::Complex<T>));
+    HIP_TRY(hipStreamCreateWithFlags(&P.aux, hipStreamNonBlocking), "create the split's stream");
+    HIP_TRY(hipEventCreateWithFlags(&P.ev_fork, hipEventDisableTiming), "create the split's events");
+    HIP_TRY(hipEventCreateWithFlags(&P.ev_long, hipEventDisableTiming), "create the split's events");
+    HIP_TRY(hipEventCreateWithFlags(&P.ev_join, hipEventDisableTiming), "create the split's events");
+  }
   HIP_TRY(hipMalloc(&P.gnodes, H.M * sizeof(ddi::Complex<T>)), "allocate node values");
   bytes += H.M * static_cast<int64_t>(sizeof(ddi::Complex<T>));
   const size_t nentries = std::max(H.sched[0].list.size(), H.sched[1].list.size());

@@ -218,6 +218,11 @@ struct DevicePlan {
   double* deconv[3] = {nullptr, nullptr, nullptr};
   double* c_half = nullptr;       // half_factor * c_q * prod(h) [M]
   double* ones = nullptr;         // [max N]: unit factors for the split's padded FFT passes
+  // split: I_1 runs on its own stream (default priority) into its own padded grid, overlapping
+  // I_2; events fork it from and join it to the caller's stream
+  void* fine_short = nullptr;     // Complex<T>[nf0*nf1*nf2]
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_long = nullptr, ev_join = nullptr;
   struct DevSchedule {
     int32_t* list = nullptr;
     SpreadItem* items = nullptr;
@@ -257,9 +262,12 @@ hipError_t run_type1(DevicePlan& P, int which, const Complex<T>* g, T* phi, int 
                      hipEvent_t* ev);
 template <typename T>
 hipError_t run_apply(DevicePlan& P, const T* rho, T* phi, int sign, hipStream_t s, hipEvent_t* ev);
-// I_1 of the split (Eq. 3.9) added to phi: padded FFT, (1 - q) Uhat, inverse FFT.
+// I_1 of the split (Eq. 3.9): padded FFT, (1 - q) Uhat, inverse FFT into fine_short (front),
+// then the last inverse pass added to phi (back).
 template <typename T>
-hipError_t run_split_short(DevicePlan& P, const T* rho, T* phi, hipStream_t s);
+hipError_t split_short_front(DevicePlan& P, const T* rho, hipStream_t s);
+template <typename T>
+hipError_t split_short_back(DevicePlan& P, T* phi, hipStream_t s);
 // The operator of the plan: run_apply, plus I_1 for a split plan (I_1 is its own transpose).
 template <typename T>
 hipError_t run_ddi(DevicePlan& P, const T* rho, T* phi, int sign, hipStream_t s, hipEvent_t* ev);

@@ -976,17 +976,17 @@ hipError_t run_apply(DevicePlan& P, const T* rho, T* phi, int sign, hipStream_t 
   return run_type1<T>(P, kHalf, g, phi, sign, s, ev);
 }
 
-// I_1 of the split (Eq. 3.9), added to phi.  The box is zero-padded to the fine grid (2 N_i
-// points, k_m = 2 pi m / (2 N_i h_i)); the density enters without deconvolution.  Only the modes
+// I_1 of the split (Eq. 3.9).  The box is zero-padded to the fine grid (2 N_i points,
+// k_m = 2 pi m / (2 N_i h_i)); the density enters without deconvolution.  Only the modes
 // m2 in [0, N2) are formed (a real field's half set; m2 = -N2 is a Nyquist plane): last-axis
 // FFT with padding, axis-1 FFT, then one pass that transforms axis 0, multiplies by
-// (1 - q) Uhat and transforms back, axis-1 inverse, last-axis inverse with truncation, real
-// part and accumulation.
+// (1 - q) Uhat and transforms back, axis-1 inverse (front); last-axis inverse with truncation,
+// real part and accumulation into phi (back).  Works in fine_short.
 template <typename T>
-hipError_t run_split_short(DevicePlan& P, const T* rho, T* phi, hipStream_t s) {
+hipError_t split_short_front(DevicePlan& P, const T* rho, hipStream_t s) {
   const HostTables& H = P.H;
-  if (!H.split || H.dim != 3 || !P.ones) return hipErrorInvalidValue;
-  C<T>* F = reinterpret_cast<C<T>*>(P.fine);
+  if (!H.split || H.dim != 3 || !P.ones || !P.fine_short) return hipErrorInvalidValue;
+  C<T>* F = reinterpret_cast<C<T>*>(P.fine_short);
   const int nz = H.N[2];
   const C<T>* tw0 = reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[0])]);
   const C<T>* tw1 = reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[1])]);
@@ -1007,20 +1007,39 @@ hipError_t run_split_short(DevicePlan& P, const T* rho, T* phi, hipStream_t s) {
   DDI_CHECK((launch_symbol<T>(H.nf[0], F, H.nf[1], H.nf[2], H.N[0], nz, sp, tw0, s)));
   DDI_CHECK((launch_strided<T, 1>(H.nf[1], F, 1, H.nf[0], H.nf[1], H.nf[2], H.N[0], 1, H.N[1], 0, 1, H.N[1], 0, nz,
                                   tw1, s)));
-  DDI_CHECK((launch_contig<T, 1, C2R_ADD>(H.nf[2], F, phi, H.N[0], H.N[1], H.nf[0], H.nf[1], H.N[2], 0, nz, P.ones,
-                                          P.ones, P.ones, tw2, s)));
   return hipSuccess;
 }
 
 template <typename T>
-hipError_t run_ddi(DevicePlan& P, const T* rho, T* phi, int sign, hipStream_t s, hipEvent_t* ev) {
-  DDI_CHECK(run_apply<T>(P, rho, phi, sign, s, ev));
-  if (P.H.split) DDI_CHECK(run_split_short<T>(P, rho, phi, s));
-  return hipSuccess;
+hipError_t split_short_back(DevicePlan& P, T* phi, hipStream_t s) {
+  const HostTables& H = P.H;
+  if (!H.split || H.dim != 3 || !P.ones || !P.fine_short) return hipErrorInvalidValue;
+  const C<T>* tw2 = reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[2])]);
+  return launch_contig<T, 1, C2R_ADD>(H.nf[2], P.fine_short, phi, H.N[0], H.N[1], H.nf[0], H.nf[1], H.N[2], 0,
+                                      H.N[2], P.ones, P.ones, P.ones, tw2, s);
 }
 
-template hipError_t run_split_short<double>(DevicePlan&, const double*, double*, hipStream_t);
-template hipError_t run_split_short<float>(DevicePlan&, const float*, float*, hipStream_t);
+// The operator of the plan.  Split: I_1's front runs on the plan's own stream while I_2 runs on
+// s; I_1's last pass adds into phi once I_2 has written it, and s waits for it (I_1 is its own
+// transpose, so the adjoint takes the same I_1).
+template <typename T>
+hipError_t run_ddi(DevicePlan& P, const T* rho, T* phi, int sign, hipStream_t s, hipEvent_t* ev) {
+  if (!P.H.split) return run_apply<T>(P, rho, phi, sign, s, ev);
+  DDI_CHECK(hipEventRecord(P.ev_fork, s));
+  DDI_CHECK(hipStreamWaitEvent(P.aux, P.ev_fork, 0));
+  DDI_CHECK(split_short_front<T>(P, rho, P.aux));
+  DDI_CHECK(run_apply<T>(P, rho, phi, sign, s, ev));
+  DDI_CHECK(hipEventRecord(P.ev_long, s));
+  DDI_CHECK(hipStreamWaitEvent(P.aux, P.ev_long, 0));
+  DDI_CHECK(split_short_back<T>(P, phi, P.aux));
+  DDI_CHECK(hipEventRecord(P.ev_join, P.aux));
+  return hipStreamWaitEvent(s, P.ev_join, 0);
+}
+
+template hipError_t split_short_front<double>(DevicePlan&, const double*, hipStream_t);
+template hipError_t split_short_front<float>(DevicePlan&, const float*, hipStream_t);
+template hipError_t split_short_back<double>(DevicePlan&, double*, hipStream_t);
+template hipError_t split_short_back<float>(DevicePlan&, float*, hipStream_t);
 template hipError_t run_ddi<double>(DevicePlan&, const double*, double*, int, hipStream_t, hipEvent_t*);
 template hipError_t run_ddi<float>(DevicePlan&, const float*, float*, int, hipStream_t, hipEvent_t*);
 template hipError_t run_type2<double>(DevicePlan&, int, const double*, Complex<double>*, const double*, double,
