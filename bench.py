@@ -173,15 +173,9 @@ def cpu_baseline(wl, rho, dip, M_eff, target_s):
                       f"evals/s = (sample/M_eff)/time"}
 
 
-def other_workloads(args, torch, np, I, DDIPlan):
-    """The remaining workloads, each timed on its own plan: the split of Eq. 3.9 on the c2_128 input,
-    quasi-2D 512^2 FP64 (c3_512), 3D 256^3 mixed (c4_256) and the 128^3 ground-state gradient flow
-    (c5_gf, 200 steps)."""
-    from paper_1504_02897_amd.gf import ground_state
-    res = {}
+def split_workload(args, torch, np, I, DDIPlan):
+    """The split of Eq. 3.9 on the c2_128 input (FP64 and mixed), beside the full-ball FP64 apply."""
     reps = max(5, args.steps // 2)
-
-    # the split of Eq. 3.9 on the c2_128 input: I_1 by the zero-padded FFT, I_2 on a small ball
     name = "c2_128"
     wl = I.WORKLOADS[name]
     d = I.mixture_workload(name, seed=args.seed)
@@ -210,8 +204,19 @@ def other_workloads(args, torch, np, I, DDIPlan):
                        "s": round(p.info["split_s"], 6), "ball_radius": round(p.info["kmax"], 6),
                        "rel_linf_diff_vs_full_ball": err}
         del p, rr, o, a
-    res["c2_split"] = split
     del r
+    return split
+
+
+def other_workloads(args, torch, np, I, DDIPlan):
+    """The remaining workloads, each timed on its own plan: the split of Eq. 3.9 on the c2_128 input,
+    quasi-2D 512^2 FP64 (c3_512), 3D 256^3 mixed (c4_256) and the 128^3 ground-state gradient flow
+    (c5_gf, 200 steps)."""
+    from paper_1504_02897_amd.gf import ground_state
+    res = {}
+    reps = max(5, args.steps // 2)
+
+    res["c2_split"] = split_workload(args, torch, np, I, DDIPlan)
 
     name = "c3_512"
     wl = I.WORKLOADS[name]
@@ -329,6 +334,8 @@ def main():
     ap.add_argument("--profile-reps", type=int, default=10)
     ap.add_argument("--headline-only", action="store_true",
                     help="skip the 2D, 256^3 mixed and gradient-flow workloads")
+    ap.add_argument("--split-only", action="store_true",
+                    help="time only the split of Eq. 3.9 on the c2_128 input and print its JSON object")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see the sharding notes); "
@@ -342,6 +349,9 @@ def main():
     from paper_1504_02897_amd.ddi import DDIPlan
 
     torch.cuda.set_device(0)
+    if args.split_only:
+        print(json.dumps({"c2_split": split_workload(args, torch, np, I, DDIPlan)}), flush=True)
+        return
     name = "c2_128"
     wl = I.WORKLOADS[name]
     data = I.mixture_workload(name, seed=args.seed)
