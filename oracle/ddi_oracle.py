@@ -514,6 +514,21 @@ def ts_step(psi_n: np.ndarray, prob: DDIProblem, gp: GPEParams, dt: float, delta
     return np.fft.ifftn(kin * np.fft.fftn(psi2))
 
 
+def ts_steps_rotating(psi0: np.ndarray, prob: DDIProblem, gp: GPEParams, t0: float, dt: float, steps: int,
+                      axis) -> np.ndarray:
+    """Eq. tssp2 (Case I, delta = 0) with a time-dependent dipole axis n(t) = m(t) = axis(t), as
+    in Eq. dip_rot.  G of Eq. fun2 is lam int_{t_n}^{t_{n+1}} U_dip(., tau) * rho dtau; it is taken
+    by the midpoint rule, lam dt U_dip(., t_n + dt/2) * rho (a reading: second order, like the
+    splitting).  Each step sets the problem's axis and then takes ts_step."""
+    psi = np.asarray(psi0, dtype=np.complex128)
+    for j in range(steps):
+        prob.dip_n = tuple(float(v) for v in axis(t0 + (j + 0.5) * dt))
+        prob.dip_m = None
+        prob._cache.clear()                  # the node coefficients depend on the axis
+        psi = ts_step(psi, prob, gp, dt)
+    return psi
+
+
 # --------------------------------------------------------------------------
 # Error metrics (Eq. error_l2 and the relative max-norm)
 # --------------------------------------------------------------------------

@@ -142,3 +142,8 @@ def random_field(seed, shape, complex_=False):
     if complex_:
         return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
     return rng.standard_normal(shape)
+
+
+def dip_rot(t):
+    """The rotating dipole orientation of the dynamics example: n(t) = (sin(t/5), 0, cos(t/5))."""
+    return np.array([math.sin(t / 5.0), 0.0, math.cos(t / 5.0)])

@@ -584,3 +584,39 @@ def test_split_short_range_symmetric_and_radial_invariant():
     i1 = O.split_short_range(rho, prob, s)
     assert abs(np.sum(rho * i1)) < 1e-13 * np.sum(np.abs(rho * i1))
     assert np.max(np.abs(i1)) > 1e-3 * np.max(rho)
+
+
+# ---------------------------------------------------------------- time-dependent dipole axis
+def _rot(w):
+    return lambda t: np.array([math.sin(w * t), 0.0, math.cos(w * t)])
+
+
+def test_rotating_axis_with_a_constant_axis_is_the_fixed_step():
+    p, gp, psi = _ts_case()
+    n0 = np.array(p.dip_n)
+    got = O.ts_steps_rotating(psi, p, gp, 0.0, 0.01, 3, lambda t: n0)
+    q = O.DDIProblem(dim=3, n=p.n, L=p.L, dip_n=tuple(n0), n_rad=p.n_rad, n_pol=p.n_pol, n_azi=p.n_azi)
+    ref = psi
+    for _ in range(3):
+        ref = O.ts_step(ref, q, gp, dt=0.01)
+    assert np.max(np.abs(got - ref)) < 1e-14 * np.max(np.abs(psi))
+
+
+def test_rotating_axis_midpoint_rule_is_second_order():
+    """With the axis turning fast (n(t) = (sin 5t, 0, cos 5t)) the self-convergence of the scheme at
+    T = 0.24 is second order; taking the axis at the start of each step instead (a plausible
+    mistake) leaves a first-order error, which this ratio would show.  The mass is conserved."""
+    p, gp, psi0 = _ts_case()
+    T, ax = 0.24, _rot(5.0)
+    ref = O.ts_steps_rotating(psi0, p, gp, 0.0, T / 96, 96, ax)
+    errs = []
+    for steps in (6, 12, 24):
+        got = O.ts_steps_rotating(psi0, p, gp, 0.0, T / steps, steps, ax)
+        errs.append(float(np.max(np.abs(got - ref))))
+        assert abs(_mass(got, p) - _mass(psi0, p)) < 1e-12 * _mass(psi0, p)
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.2 < r1 < 4.8 and 3.2 < r2 < 4.8, errs
+    # the start-of-step axis: first order
+    bad = [O.ts_steps_rotating(psi0, p, gp, -0.5 * T / s, T / s, s, ax) for s in (12, 24)]
+    e_bad = [float(np.max(np.abs(b - ref))) for b in bad]
+    assert e_bad[0] / e_bad[1] < 2.6
