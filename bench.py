@@ -320,6 +320,42 @@ def other_workloads(args, torch, np, I, DDIPlan):
         "ours": {"E": E, "mu": mu, "kin": ek, "pot": ep, "int": ei, "dip": ed,
                  "virial": 2 * ek - 2 * ep + 3 * ei + 3 * ed},
         "paper": {"E": 2.1838, "mu": 2.7011, "kin": 0.44525, "pot": 1.2212, "int": 1.5749, "dip": -1.0576}}
+    del p, psi0
+
+    # the rotating-dipole example (Eq. dip_rot, Case 1): the ground state for n = z in an isotropic
+    # trap, then n(t) = (sin(t/5), 0, cos(t/5)); the split plan's axes are reset before every step
+    print("[bench] c8_dip_rot", file=sys.stderr, flush=True)
+    beta8, lam8, gam8 = 103.58, 82.864, (1.0, 1.0, 1.0)
+    n8, L8 = (128,) * 3, (8.0,) * 3
+    p = DDIPlan(3, n8, L8, dip_n=(0.0, 0.0, 1.0), quad=(32, 32, 64), tol=1e-13, prec="fp64", split=True)
+    psi0 = torch.from_numpy(I.gf_initial(n8, L8, gam8)).cuda()
+    gs, hist8 = ground_state(p, psi0, beta8, lam8, gam8, dt=0.02, steps=3000, n_inner=30, energy_every=100,
+                             eps0=1e-8)
+    dt8, steps8 = 0.005, 400
+    x = gs.clone()
+    cell = p.cell
+    m0 = cell * float((x.abs() ** 2).sum())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in range(steps8):
+        p.set_dipole(I.dip_rot((j + 0.5) * dt8))
+        p.ts_step(x, beta8, lam8, gam8, dt=dt8, out=x)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    m1 = cell * float((x.abs() ** 2).sum())
+    # major axis of the density in the x-z plane (second moments), against the dipole's angle
+    rho = (x.abs() ** 2).double()
+    ax8 = torch.linspace(-L8[0], L8[0], n8[0] + 1, dtype=torch.float64, device=rho.device)[:-1]
+    X, Z = ax8.view(-1, 1, 1), ax8.view(1, 1, -1)
+    ixx, izz, ixz = float((rho * X * X).sum()), float((rho * Z * Z).sum()), float((rho * X * Z).sum())
+    res["c8_dip_rot"] = {
+        "workload": "rotating dipole (Eq. dip_rot, Case 1): ground state for beta=103.58, lambda=82.864, "
+                    "V=|x|^2/2, n=z on [-8,8)^3 at 128^3 (split plan, I_2 on 32x32x64), then time splitting "
+                    "with n(t) = (sin(t/5), 0, cos(t/5)) taken at mid-step, dt=0.005, 400 steps (t = 2), FP64",
+        "ground_state_steps": int(hist8[-1][0]), "ground_state_residual": hist8[-1][7],
+        "steps": steps8, "ms_per_step": round(1000.0 * el / steps8, 3), "mass_rel_change": m1 / m0 - 1.0,
+        "dipole_angle_from_z": 2.0 / 5.0,
+        "density_major_axis_angle_from_z": 0.5 * math.atan2(2.0 * ixz, izz - ixx)}
     return res
 
 

@@ -167,6 +167,16 @@ ddi_status ddi_apply(ddi_plan_t plan, const void* rho_dev, void* phi_dev, void* 
  * symmetric set of modes is its own transpose). */
 ddi_status ddi_apply_adjoint(ddi_plan_t plan, const void* phibar_dev, void* rhobar_dev, void* stream);
 
+/* New dipole axes for a plan (Eq. DipKer; two axes: Eq. dipmn), for a time-dependent orientation
+ * such as Eq. dip_rot: every node coefficient c_q = W_q Uhat(k_q; n, m) / (2 pi)^d (times
+ * q(k_q) for a split plan) is re-evaluated on the device from the stored nodes, and a split
+ * plan's I_1 takes the new axes.  dip_n: 3 host doubles, used as given (non-zero, finite);
+ * dip_m: NULL or all zero means m = n.  The first call on a plan allocates and uploads the node
+ * coordinates and symbol-free weights (3 M_eff doubles) and synchronises; later calls enqueue
+ * one small kernel on `stream` and allocate nothing.  Calls of the plan after it, on the same
+ * stream, see the new axes; ddi_plan_nodes returns the new coefficients. */
+ddi_status ddi_set_dipole(ddi_plan_t plan, const double* dip_n, const double* dip_m, void* stream);
+
 /* Type-2 half: rhohat_q = prod(h) sum_l rho_l exp(-i k_q . x_l) for the M_eff
  * nodes in plan order (see ddi_plan_nodes).  rhohat_dev: complex array [M_eff]. */
 ddi_status ddi_type2(ddi_plan_t plan, const void* rho_dev, void* rhohat_dev, void* stream);

@@ -48,7 +48,8 @@ void free_plan(ddi::DevicePlan& P) {
   for (hipEvent_t e : {P.ev_fork, P.ev_long, P.ev_join})
     if (e) (void)hipEventDestroy(e);
   if (P.aux) (void)hipStreamDestroy(P.aux);
-  void* ptrs[] = {P.nodes, P.c_scaled, P.c_half, P.ones, P.fine_short, P.deconv[0], P.deconv[1], P.deconv[2],
+  void* ptrs[] = {P.nodes, P.c_scaled, P.c_half, P.ones, P.fine_short, P.kq, P.base_scaled, P.base_half,
+                  P.deconv[0], P.deconv[1], P.deconv[2],
                   P.fine, P.gnodes, P.partial, P.ipartial, P.pads, P.gpe_rho, P.gpe_phi, P.gpe_phit, P.gpe_c1, P.gpe_c2, P.gpe_red};
   for (auto& d : P.dsched) {
     void* sp[] = {d.list, d.items, d.reduces, d.interp_items, d.interp_direct, d.gptr, d.gpos, d.ent};
@@ -289,10 +290,80 @@ ddi_status ddi_plan_info(ddi_plan_t plan, ddi_plan_info_t* info) {
 
 ddi_status ddi_plan_nodes(ddi_plan_t plan, int32_t* index_host, double* k_host, double* c_host) {
   if (!plan) return fail(DDI_EINVAL, "plan is NULL");
-  const ddi::HostTables& H = plan->P.H;
+  ddi::HostTables& H = plan->P.H;
+  if (H.c_stale) {
+    // the axes were changed by ddi_set_dipole: the same symbol as the plan builder, new axes
+    for (int64_t q = 0; q < H.M; ++q) {
+      const double* k = &H.k[3 * q];
+      const double kk = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+      double U;
+      if (H.dim == 3) {
+        const double kn = k[0] * H.nv[0] + k[1] * H.nv[1] + k[2] * H.nv[2];
+        const double km = k[0] * H.mv[0] + k[1] * H.mv[1] + k[2] * H.mv[2];
+        U = 3.0 * kn * km / kk - (H.nv[0] * H.mv[0] + H.nv[1] * H.mv[1] + H.nv[2] * H.mv[2]);
+      } else {
+        const double kn = k[0] * H.nv[0] + k[1] * H.nv[1];
+        const double km = k[0] * H.mv[0] + k[1] * H.mv[1];
+        U = 3.0 * (kn * km - H.nv[2] * H.mv[2] * kk) / (2.0 * std::sqrt(kk));
+      }
+      H.c[q] = H.base[q] * U;
+    }
+    H.c_stale = false;
+  }
   if (index_host) std::memcpy(index_host, H.index.data(), H.index.size() * sizeof(int32_t));
   if (k_host) std::memcpy(k_host, H.k.data(), H.k.size() * sizeof(double));
   if (c_host) std::memcpy(c_host, H.c.data(), H.c.size() * sizeof(double));
+  return DDI_OK;
+}
+
+ddi_status ddi_set_dipole(ddi_plan_t plan, const double* dip_n, const double* dip_m, void* stream) {
+  ddi_status st = check_plan(plan);
+  if (st != DDI_OK) return st;
+  if (!dip_n) return fail(DDI_EINVAL, "dip_n is NULL");
+  double n[3], m[3];
+  double nn = 0.0, mm = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    n[i] = dip_n[i];
+    m[i] = dip_m ? dip_m[i] : 0.0;
+    nn += n[i] * n[i];
+    mm += m[i] * m[i];
+  }
+  if (!(nn > 0.0) || !std::isfinite(nn)) return fail(DDI_EINVAL, "dipole axis n must be a non-zero finite vector");
+  if (!std::isfinite(mm)) return fail(DDI_EINVAL, "dipole axis m must be finite");
+  if (!(mm > 0.0)) for (int i = 0; i < 3; ++i) m[i] = n[i];
+  ddi::DevicePlan& P = plan->P;
+  const ddi::HostTables& H = P.H;
+  if (!P.kq) {
+    // first call: the node coordinates and the weights without the symbol (synchronous upload)
+    std::vector<double> bs(H.M), bh(H.M);
+    for (int64_t q = 0; q < H.M; ++q) {
+      bs[q] = H.base[q] * H.cell;
+      bh[q] = H.half_factor[q] * H.base[q] * H.cell;
+    }
+    double* d[3] = {nullptr, nullptr, nullptr};
+    const void* src[3] = {H.k.data(), bs.data(), bh.data()};
+    const size_t cnt[3] = {H.k.size(), bs.size(), bh.size()};
+    for (int i = 0; i < 3; ++i) {
+      hipError_t e = hipMalloc(reinterpret_cast<void**>(&d[i]), cnt[i] * sizeof(double));
+      if (e == hipSuccess) e = hipMemcpy(d[i], src[i], cnt[i] * sizeof(double), hipMemcpyHostToDevice);
+      if (e != hipSuccess) {
+        for (double* x : d)
+          if (x) (void)hipFree(x);
+        return hip_fail(e, "ddi_set_dipole tables");
+      }
+    }
+    P.kq = d[0];
+    P.base_scaled = d[1];
+    P.base_half = d[2];
+    P.workspace_bytes += static_cast<int64_t>((cnt[0] + cnt[1] + cnt[2]) * sizeof(double));
+  }
+  hipError_t e = ddi::run_set_dipole(P, n, m, reinterpret_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "ddi_set_dipole launch");
+  for (int i = 0; i < 3; ++i) {
+    P.H.nv[i] = n[i];
+    P.H.mv[i] = m[i];
+  }
+  P.H.c_stale = true;
   return DDI_OK;
 }
 

@@ -153,7 +153,9 @@ struct HostTables {
   // per node, plan (sorted) order
   std::vector<int32_t> index;  // [M][3]
   std::vector<double> k;       // [M][3]
-  std::vector<double> c;       // [M]  W Uhat / (2 pi)^d
+  std::vector<double> c;       // [M]  W Uhat / (2 pi)^d (times q for a split plan), for the axes nv, mv
+  std::vector<double> base;    // [M]  W / (2 pi)^d (times q): c without the symbol
+  bool c_stale = false;        // the axes changed (ddi_set_dipole): c is recomputed when read
   std::vector<int32_t> l0;     // [M][3]
   std::vector<double> wts;     // [M][3][kWMax]
   std::vector<double> deconv[3];   // 1/phihat per compact index, length N[a]
@@ -221,6 +223,11 @@ struct DevicePlan {
   // split: I_1 runs on its own stream (default priority) into its own padded grid, overlapping
   // I_2; events fork it from and join it to the caller's stream
   void* fine_short = nullptr;     // Complex<T>[nf0*nf1*nf2]
+  // ddi_set_dipole (allocated on its first call): node coordinates and the weights without the
+  // symbol, scaled as c_scaled and c_half
+  double* kq = nullptr;           // [M][3]
+  double* base_scaled = nullptr;  // base * prod(h) [M]
+  double* base_half = nullptr;    // half_factor * base * prod(h) [M]
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_long = nullptr, ev_join = nullptr;
   struct DevSchedule {
@@ -268,6 +275,8 @@ template <typename T>
 hipError_t split_short_front(DevicePlan& P, const T* rho, hipStream_t s);
 template <typename T>
 hipError_t split_short_back(DevicePlan& P, T* phi, hipStream_t s);
+// Re-evaluate c_scaled and c_half for new dipole axes from kq, base_scaled and base_half.
+hipError_t run_set_dipole(DevicePlan& P, const double* n, const double* m, hipStream_t s);
 // The operator of the plan: run_apply, plus I_1 for a split plan (I_1 is its own transpose).
 template <typename T>
 hipError_t run_ddi(DevicePlan& P, const T* rho, T* phi, int sign, hipStream_t s, hipEvent_t* ev);

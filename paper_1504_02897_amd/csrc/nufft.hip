@@ -1036,6 +1036,35 @@ hipError_t run_ddi(DevicePlan& P, const T* rho, T* phi, int sign, hipStream_t s,
   return hipStreamWaitEvent(s, P.ev_join, 0);
 }
 
+// ------------------------------------------------------------------ dipole axes
+// c = base * Uhat(k; n, m) for every node (Eq. DipKer; two axes: Eq. dipmn), in plan order.
+__global__ void __launch_bounds__(256) k_dipole_coeffs(int64_t M, int dim, const double* __restrict__ kq,
+                                                       const double* __restrict__ bs, const double* __restrict__ bh,
+                                                       double n0, double n1, double n2, double m0, double m1,
+                                                       double m2, double* __restrict__ cs, double* __restrict__ ch) {
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= M) return;
+  const double k0 = kq[3 * q], k1 = kq[3 * q + 1], k2 = kq[3 * q + 2];
+  const double kk = k0 * k0 + k1 * k1 + k2 * k2;
+  double U;
+  if (dim == 3) {
+    U = 3.0 * (k0 * n0 + k1 * n1 + k2 * n2) * (k0 * m0 + k1 * m1 + k2 * m2) / kk - (n0 * m0 + n1 * m1 + n2 * m2);
+  } else {
+    U = 3.0 * ((k0 * n0 + k1 * n1) * (k0 * m0 + k1 * m1) - n2 * m2 * kk) / (2.0 * sqrt(kk));
+  }
+  cs[q] = bs[q] * U;
+  ch[q] = bh[q] * U;
+}
+
+hipError_t run_set_dipole(DevicePlan& P, const double* n, const double* m, hipStream_t s) {
+  const int64_t M = P.H.M;
+  if (!P.kq || !P.base_scaled || !P.base_half || M <= 0) return hipErrorInvalidValue;
+  const int blocks = static_cast<int>((M + 255) / 256);
+  hipLaunchKernelGGL(k_dipole_coeffs, dim3(blocks), dim3(256), 0, s, M, P.H.dim, P.kq, P.base_scaled, P.base_half,
+                     n[0], n[1], n[2], m[0], m[1], m[2], P.c_scaled, P.c_half);
+  return hipGetLastError();
+}
+
 template hipError_t split_short_front<double>(DevicePlan&, const double*, hipStream_t);
 template hipError_t split_short_front<float>(DevicePlan&, const float*, hipStream_t);
 template hipError_t split_short_back<double>(DevicePlan&, double*, hipStream_t);

@@ -432,7 +432,7 @@ std::string build_tables(const ddi_params& p, HostTables& t, int* status) {
   t.m_nominal = static_cast<int64_t>(p.n_rad) * npol * nazi;
 
   std::vector<int32_t> idx_nat;
-  std::vector<double> k_nat, c_nat;
+  std::vector<double> k_nat, c_nat, base_nat;
   for (int ia = 0; ia < p.n_rad; ++ia) {
     double r = 0.5 * kmax * (1.0 + tr[ia]);
     double wrad = 0.5 * kmax * wr[ia];
@@ -478,6 +478,7 @@ std::string build_tables(const ddi_params& p, HostTables& t, int* status) {
         // split: I_2 carries q(k) = exp(-|k|^2/s^2)
         const double qk = t.split ? std::exp(-kk / (split_s * split_s)) : 1.0;
         c_nat.push_back(W * U * inv2pid * qk);
+        base_nat.push_back(W * inv2pid * qk);
       }
     }
   }
@@ -541,6 +542,7 @@ std::string build_tables(const ddi_params& p, HostTables& t, int* status) {
   t.index.resize(3 * M);
   t.k.resize(3 * M);
   t.c.resize(M);
+  t.base.resize(M);
   t.half_factor.resize(M);
   t.l0.resize(3 * M);
   t.wts.resize(static_cast<size_t>(3 * kWMax) * M);
@@ -553,6 +555,7 @@ std::string build_tables(const ddi_params& p, HostTables& t, int* status) {
       t.l0[3 * s + a] = l0_nat[3 * q + a];
     }
     t.c[s] = c_nat[q];
+    t.base[s] = base_nat[q];
     t.half_factor[s] = hf_nat[q];
     key[s] = home[q];
     std::memcpy(&t.wts[static_cast<size_t>(s) * 3 * kWMax], &w_nat[static_cast<size_t>(q) * 3 * kWMax],

@@ -53,7 +53,7 @@ class PlanInfo(ctypes.Structure):
 
 
 EXPORTED = ["ddi_plan", "ddi_apply", "ddi_apply_adjoint", "ddi_type2", "ddi_type1", "gpe_energy_grad",
-            "gpe_gf_step", "gpe_ts_step", "ddi_profile_apply", "ddi_plan_info", "ddi_plan_nodes", "ddi_destroy", "ddi_last_error"]
+            "gpe_gf_step", "gpe_ts_step", "ddi_set_dipole", "ddi_profile_apply", "ddi_plan_info", "ddi_plan_nodes", "ddi_destroy", "ddi_last_error"]
 STAGES = ["fft_last_pad", "fft_axis1_t2", "fft_axis0_t2", "interp", "spread", "spread_reduce", "fft_axis0_t1",
           "fft_axis1_t1", "fft_last_trunc"]
 
@@ -69,6 +69,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.gpe_energy_grad.argtypes = [vp, ctypes.POINTER(GPEParamsC), vp, ctypes.POINTER(f64), vp, vp]
     lib.gpe_gf_step.argtypes = [vp, ctypes.POINTER(GPEParamsC), f64, i32, vp, vp, vp]
     lib.gpe_ts_step.argtypes = [vp, ctypes.POINTER(GPEParamsC), f64, f64, vp, vp, vp]
+    lib.ddi_set_dipole.argtypes = [vp, ctypes.POINTER(f64), ctypes.POINTER(f64), vp]
     lib.ddi_profile_apply.argtypes = [vp, vp, vp, i32, i32, ctypes.POINTER(f64), vp]
     lib.ddi_plan_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
     lib.ddi_plan_nodes.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(f64), ctypes.POINTER(f64)]
@@ -256,6 +257,12 @@ class DDIPlan:
         _check(_lib.gpe_ts_step(self._h, ctypes.byref(gp), float(dt), float(delta), _ptr(psi), _ptr(out),
                                 _stream()))
         return out
+
+    def set_dipole(self, dip_n, dip_m=None):
+        """New dipole axes (ddi_set_dipole): the node coefficients are re-evaluated on the device."""
+        n = (ctypes.c_double * 3)(*[float(v) for v in dip_n])
+        m = None if dip_m is None else (ctypes.c_double * 3)(*[float(v) for v in dip_m])
+        _check(_lib.ddi_set_dipole(self._h, n, m, _stream()))
 
     def nodes(self):
         """(index [M,3] int32, k [M,3] float64, c [M] float64) in plan order."""
