@@ -252,7 +252,19 @@ def other_workloads(args, torch, np, I, DDIPlan):
                            "fwd_adj_ms": round(fa, 4), "m_eff": p.m_eff,
                            "roofline": roofline_of(dom, st[dom], model, FP32_PEAK_TFLOPS),
                            "stages_ms": {k: round(v, 4) for k, v in st.items()}}
-    del p, r, o, a
+    # the same input by the split of Eq. 3.9 (I_1 on the 512^3 padded grid, I_2 on 16x16x32 nodes)
+    print("[bench] c4_256 split", file=sys.stderr, flush=True)
+    ref4 = o.double().cpu().numpy()
+    q = DDIPlan(3, wl["n"], wl["L"], dip_n=tuple(d["dip_n"]), quad=(16, 16, 32), tol=wl["tol"], prec="mixed",
+                split=True)
+    ms = time_steps(lambda: q.apply(r, out=o), reps, 3, torch)
+    q.apply(r, out=o)
+    res["c4_256_split_mixed"] = {
+        "workload": "c4_256 input by the split of Eq. 3.9, mixed: I_1 on the 512^3 zero-padded grid, I_2 on "
+                    "16x16x32 nodes",
+        "value": round(1000.0 / ms, 2), "unit": "evals/s", "ms_per_step": round(ms, 4), "m_eff": q.m_eff,
+        "rel_linf_diff_vs_full_ball": float(np.max(np.abs(o.double().cpu().numpy() - ref4)) / np.max(np.abs(ref4)))}
+    del p, q, r, o, a
 
     name = "c5_gf"
     wl = I.WORKLOADS[name]

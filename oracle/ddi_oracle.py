@@ -420,7 +420,7 @@ def fourier_mu2(prob: DDIProblem) -> np.ndarray:
     return sum(g * g for g in grids)
 
 
-def gpe_energy_grad(psi: np.ndarray, prob: DDIProblem, gp: GPEParams, grad: bool = True):
+def gpe_energy_grad(psi: np.ndarray, prob: DDIProblem, gp: GPEParams, grad: bool = True, ops=None):
     """Energy parts (Sec. 3.2) and G = dE_h / d conj(psi) on the grid.
 
     E_kin = 1/2 prod(h)/prod(N) sum_p |mu_p|^2 |psihat_p|^2      (psihat: DFT of psi)
@@ -429,13 +429,16 @@ def gpe_energy_grad(psi: np.ndarray, prob: DDIProblem, gp: GPEParams, grad: bool
     E_dip = lam/2 prod(h) sum Phi |psi|^2, Phi = A |psi|^2
     G     = prod(h) [ -1/2 Lap psi + V psi + beta |psi|^2 psi + lam/2 (A rho + A^T rho) psi ]
     Returns (E, G) with E = [kin, pot, int, dip, total]; G is None if not grad.
-    The DFT over the grid is numpy's FFT (a library step).
+    The DFT over the grid is numpy's FFT (a library step).  ops: optional (A, A^T) as callables
+    on real grids (e.g. the split of Eq. 3.9); ddi_apply and ddi_apply_adjoint otherwise.
     """
+    apply_A, apply_At = ops if ops is not None else (lambda r: ddi_apply(r, prob),
+                                                     lambda r: ddi_apply_adjoint(r, prob))
     psi = np.asarray(psi, dtype=np.complex128)
     cell = prob.cell
     rho = (psi.real ** 2 + psi.imag ** 2)
     V = trap_potential(prob, gp)
-    phi = ddi_apply(rho, prob)
+    phi = apply_A(rho)
     psih = np.fft.fftn(psi)
     mu2 = fourier_mu2(prob)
     ntot = float(np.prod(prob.n))
@@ -447,7 +450,7 @@ def gpe_energy_grad(psi: np.ndarray, prob: DDIProblem, gp: GPEParams, grad: bool
     if not grad:
         return E, None
     lap_term = np.fft.ifftn(0.5 * mu2 * psih)          # -1/2 Lap psi
-    phit = ddi_apply_adjoint(rho, prob)
+    phit = apply_At(rho)
     G = cell * (lap_term + V * psi + gp.beta * rho * psi + 0.5 * gp.lam * (phi + phit) * psi)
     return E, G
 
