@@ -190,3 +190,29 @@ def test_split_gpe_energy_and_gradient_fp64():
     assert errE <= FP64_TOL and errG <= FP64_TOL
     # the dipolar part differs from the full-ball plan's on this grid (a different operator)
     assert abs(E_ref[3]) > 1e-6
+
+
+def test_split_type2_type1_act_on_the_small_ball_and_profile_runs():
+    """ddi_type2 / ddi_type1 of a split plan are the NUFFT halves over the I_2 nodes (without q
+    and without I_1); ddi_profile_apply returns the stage times and the operator's output."""
+    n, L = (32, 32, 32), (8.0, 8.0, 8.0)
+    say("case: split fp64 type2/type1/profile 32^3")
+    plan, prob, s = make_split(n, L, (12, 12, 24), (0.48, -0.6, 0.64))
+    rho = I.c1_density(n, L)
+    idx, _, _ = plan.nodes()
+    quad = O.quadrature(prob)
+    key = {tuple(t): i for i, t in enumerate(quad.index.tolist())}
+    rows = np.array([key[tuple(t)] for t in idx.tolist()])
+    kq = quad.k[rows]
+    rh = plan.type2(to_dev(rho, torch.float64)).cpu().numpy()
+    ref = O.rhohat(rho, prob, kq)
+    assert float(np.max(np.abs(rh - ref)) / np.max(np.abs(ref))) < 1e-13
+    g = I.random_field(5, (plan.m_eff,), complex_=True)
+    phi = plan.type1(to_dev(g, torch.complex128)).cpu().numpy()
+    assert relinf(phi, O.nodes_to_grid(g, prob, kq)) <= FP64_TOL
+    x = to_dev(rho, torch.float64)
+    out = torch.empty_like(x)
+    st = plan.profile(x, reps=2, out=out)
+    assert len(st) == 9 and all(v >= 0.0 for v in st.values())
+    torch.cuda.synchronize()
+    assert relinf(out.cpu().numpy(), O.split_apply(rho, prob, s)) <= FP64_TOL
