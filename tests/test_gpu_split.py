@@ -216,3 +216,21 @@ def test_split_type2_type1_act_on_the_small_ball_and_profile_runs():
     assert len(st) == 9 and all(v >= 0.0 for v in st.values())
     torch.cuda.synchronize()
     assert relinf(out.cpu().numpy(), O.split_apply(rho, prob, s)) <= FP64_TOL
+
+
+def test_split_parameter_defaults():
+    """s and the ball radius when only some are given: tol from the kernel width (10^-(w-1)) when
+    tol is 0, and the radius s sqrt(ln(1/tol)) for an explicit s; the result still matches."""
+    n, L = (32, 32, 32), (8.0, 8.0, 8.0)
+    say("case: split defaults (kernel_width without tol; explicit s, default radius)")
+    p = DDIPlan(3, n, L, quad=(16, 16, 32), tol=0.0, kernel_width=14, split=True)
+    lt = math.log(1e13)
+    assert abs(p.info["split_s"] - math.sqrt(lt) / 8.0) <= 1e-14
+    assert abs(p.info["kmax"] - lt / 8.0) <= 1e-13
+    q = DDIPlan(3, n, L, quad=(16, 16, 32), tol=1e-13, split=True, split_s=0.8)
+    assert abs(q.info["kmax"] - 0.8 * math.sqrt(lt)) <= 1e-13
+    prob = O.DDIProblem(dim=3, n=n, L=L, dip_n=(0.0, 0.0, 1.0), n_rad=16, n_pol=16, n_azi=32,
+                        kmax=0.8 * math.sqrt(lt))
+    rho = I.c1_density(n, L)
+    phi = q.apply(to_dev(rho, torch.float64)).cpu().numpy()
+    assert relinf(phi, O.split_apply(rho, prob, 0.8)) <= FP64_TOL
