@@ -61,6 +61,8 @@ class DDIProblem:
     n_rad, n_pol, n_azi : quadrature sizes (n_pol unused in 2D).
     kmax    : radius of the Fourier ball; <= 0 selects pi*sqrt(sum 1/h^2).
     mask    : drop nodes outside the Nyquist box.
+    stretch : per-axis factors S_i of the quadrature (k = S k' with k' on the spherical/polar
+              rule, weights times det S); (1, 1, 1) is the rule of Eq. DDI-Trun1 itself.
     """
 
     dim: int
@@ -73,6 +75,7 @@ class DDIProblem:
     n_azi: int = 32
     kmax: float = 0.0
     mask: bool = True
+    stretch: tuple = (1.0, 1.0, 1.0)
     _cache: dict = field(default_factory=dict, repr=False, compare=False)
 
     @property
@@ -90,9 +93,11 @@ class DDIProblem:
                 for Li, hi, ni in zip(self.L, self.h, self.n)]
 
     def kmax_value(self):
+        """Radius of the ball in k' (= k without stretch): the circumradius of the Nyquist box
+        seen through the stretch, pi sqrt(sum 1/(h_i S_i)^2), unless given."""
         if self.kmax > 0:
             return float(self.kmax)
-        return math.pi * math.sqrt(sum(1.0 / hi ** 2 for hi in self.h))
+        return math.pi * math.sqrt(sum(1.0 / (hi * si) ** 2 for hi, si in zip(self.h, self.stretch)))
 
 
 # --------------------------------------------------------------------------
@@ -153,6 +158,7 @@ def quadrature(prob: DDIProblem, apply_mask: bool | None = None) -> Quadrature:
         W = w^r_a r_a^2 w^u_b (2 pi / N_phi).
     2D: k = r (cos phi, sin phi), W = w^r_a r_a (2 pi / N_phi).
     Nodes with |k_i| > pi / h_i on some axis are removed when masking.
+    With a stretch S (a reading for anisotropic boxes): k = S k', W = W' det S.
     """
     if apply_mask is None:
         apply_mask = prob.mask
@@ -179,6 +185,9 @@ def quadrature(prob: DDIProblem, apply_mask: bool | None = None) -> Quadrature:
         index = np.stack([a, np.zeros_like(a), c], axis=1)
     else:
         raise ValueError("dim must be 2 or 3")
+    S = np.asarray(prob.stretch[:prob.dim], dtype=np.float64)
+    k = k * S[None, :]
+    W = W * float(np.prod(S))
     n_nom = k.shape[0]
     if apply_mask:
         lim = np.array([math.pi / hi for hi in prob.h])

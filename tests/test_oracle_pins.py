@@ -620,3 +620,46 @@ def test_rotating_axis_midpoint_rule_is_second_order():
     bad = [O.ts_steps_rotating(psi0, p, gp, -0.5 * T / s, T / s, s, ax) for s in (12, 24)]
     e_bad = [float(np.max(np.abs(b - ref))) for b in bad]
     assert e_bad[0] / e_bad[1] < 2.6
+
+
+# ---------------------------------------------------------------- stretched quadrature (anisotropic boxes)
+def test_stretched_weights_integrate_the_ellipsoid():
+    """k = S k' with weights times det S: unmasked, the weights sum to the ellipsoid's volume
+    (4/3) pi Kmax'^3 S_x S_y S_z, and the default Kmax' is the circumradius of the Nyquist box
+    seen through the stretch."""
+    S = (1.0, 2.0, 4.0)
+    p = O.DDIProblem(dim=3, n=(16, 16, 16), L=(8.0, 4.0, 2.0), n_rad=8, n_pol=4, n_azi=6, mask=False, stretch=S)
+    q = O.quadrature(p)
+    vol = 4.0 / 3.0 * math.pi * q.kmax ** 3 * 8.0
+    assert abs(q.W.sum() - vol) < 1e-12 * vol
+    assert abs(q.kmax - math.pi * math.sqrt(3.0)) < 1e-12          # h_i S_i = 1 on every axis
+    # the nodes are those of the unstretched rule with the same radius, scaled axis by axis
+    p1 = O.DDIProblem(dim=3, n=(16, 16, 16), L=(8.0, 4.0, 2.0), n_rad=8, n_pol=4, n_azi=6, mask=False,
+                      kmax=q.kmax)
+    q1 = O.quadrature(p1)
+    assert np.max(np.abs(q.k - q1.k * np.array(S))) < 1e-13 * q.kmax
+
+
+def test_stretched_quadrature_resolves_a_z_localized_gaussian():
+    """The z-localized density of Eq. Coulomb:3D:aniso:z (scaled) on [-L, L]^2 x [-eps L, eps L] with
+    h_z = eps h_x: with the stretch (1, 1, 1/eps) the quadrature resolves the transform's long axis
+    and reaches the exact DDI (Ex. 2.3 integrals) to 1e-6 at 61k nodes; the plain rule is off by
+    1e-2 at a similar count."""
+    eps = 0.25
+    n, L = (32, 32, 32), (6.0, 6.0, 6.0 * eps)
+    a = np.array([0.5, 0.5, 0.5 * eps * eps])
+    xs = I.grid_axes(n, L)
+    X = np.meshgrid(*xs, indexing="ij")
+    rho = np.prod([R.heat_kernel(a[i], X[i]) for i in range(3)], axis=0)
+    rng = np.random.default_rng(2)
+    pts = np.concatenate([rng.integers(0, 32, size=(10, 3)), np.array([[16, 16, 16], [16, 16, 17], [18, 16, 16]])])
+    ex = np.array([R.phi_gaussian_product([xs[0][p[0]], xs[1][p[1]], xs[2][p[2]]], a, [0, 0, 0], (0.6, 0, 0.8))
+                   for p in pts])
+    errs = {}
+    for st in ((1.0, 1.0, 1.0), (1.0, 1.0, 1.0 / eps)):
+        prob = O.DDIProblem(dim=3, n=n, L=L, dip_n=(0.6, 0.0, 0.8), n_rad=48, n_pol=32, n_azi=64, stretch=st)
+        quad, c = O.ddi_nodes(prob)
+        got = O.nodes_to_points(c * O.rhohat(rho, prob, quad.k), prob, quad.k, pts)
+        errs[st[2]] = float(np.max(np.abs(got - ex)) / np.max(np.abs(ex)))
+    assert errs[1.0 / eps] < 2e-6, errs
+    assert errs[1.0] > 1e-3, errs
