@@ -100,6 +100,12 @@ typedef enum { DDI_FP64 = 0, DDI_MIXED = 1 } ddi_precision;
  *               exp(-s^2 r^2/4) of the short-range kernel at tol at the
  *               nearest image 2 L_min away.  With kernel_width set and tol
  *               outside (0, 1), tol is taken as 10^-(w-1).
+ *  stretch[3]   per-axis factors S_i of the quadrature (a reading for anisotropic
+ *               boxes such as Tables 4-5): nodes k = S k' with k' on the rule
+ *               above, weights times det S; the Jacobian still cancels the
+ *               singularity (Uhat is homogeneous of degree 0).  kmax (of k')
+ *               <= 0 then selects pi sqrt(sum 1/(h_i S_i)^2).  Values <= 0 mean
+ *               1 (the plain rule); stretch[2] is ignored in 2D.
  */
 typedef struct {
   int32_t dim;
@@ -115,6 +121,7 @@ typedef struct {
   int32_t kernel_width;
   int32_t split;
   double split_s;
+  double stretch[3];
 } ddi_params;
 
 /*

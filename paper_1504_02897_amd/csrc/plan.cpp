@@ -353,6 +353,8 @@ std::string build_tables(const ddi_params& p, HostTables& t, int* status) {
   if (w < 2 || w > kWMax) return "kernel_width must lie in [2, 16]";
   if (p.split != 0 && p.split != 1) return "split must be 0 or 1";
   if (p.split && !std::isfinite(p.split_s)) return "split_s must be finite";
+  for (int a = 0; a < 3; ++a)
+    if (!std::isfinite(p.stretch[a])) return "stretch must be finite";
 
   *status = DDI_ENOTSUP;
   if (p.split && d != 3) return "the split of Eq. 3.9 is built for 3D only";
@@ -398,13 +400,22 @@ std::string build_tables(const ddi_params& p, HostTables& t, int* status) {
   }
   t.split = p.split != 0;
   t.split_s = split_s;
+  // stretched rule (anisotropic boxes): k = S k', W = W' det S; kmax is the radius in k'
+  double S[3] = {1.0, 1.0, 1.0};
+  double detS = 1.0;
+  for (int a = 0; a < d; ++a) {
+    S[a] = p.stretch[a] > 0.0 ? p.stretch[a] : 1.0;
+    detS *= S[a];
+  }
   double kmax = p.kmax;
   if (!(kmax > 0.0)) {
     if (p.split) {
-      kmax = split_s * std::sqrt(ln_tol);
+      double smin = S[0];
+      for (int a = 1; a < d; ++a) smin = std::min(smin, S[a]);
+      kmax = split_s * std::sqrt(ln_tol) / smin;   // the ellipsoid holds the ball where q matters
     } else {
       double s = 0.0;
-      for (int a = 0; a < d; ++a) s += 1.0 / (hp[a] * hp[a]);
+      for (int a = 0; a < d; ++a) s += 1.0 / (hp[a] * S[a] * hp[a] * S[a]);
       kmax = M_PI * std::sqrt(s);
     }
   }
@@ -453,6 +464,8 @@ std::string build_tables(const ddi_params& p, HostTables& t, int* status) {
           k[2] = 0.0;
           W = wrad * r * wphi;
         }
+        for (int a = 0; a < d; ++a) k[a] *= S[a];
+        W *= detS;
         if (p.nyquist_mask) {
           bool inside = true;
           for (int a = 0; a < d; ++a) inside = inside && (std::fabs(k[a]) <= M_PI / hp[a]);

@@ -34,7 +34,7 @@ class DDIParams(ctypes.Structure):
                 ("n_rad", ctypes.c_int64), ("n_pol", ctypes.c_int64), ("n_azi", ctypes.c_int64),
                 ("kmax", ctypes.c_double), ("nyquist_mask", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("prec", ctypes.c_int32), ("kernel_width", ctypes.c_int32),
-                ("split", ctypes.c_int32), ("split_s", ctypes.c_double)]
+                ("split", ctypes.c_int32), ("split_s", ctypes.c_double), ("stretch", ctypes.c_double * 3)]
 
 
 class GPEParamsC(ctypes.Structure):
@@ -109,10 +109,13 @@ class DDIPlan:
     split, split_s   the split of Eq. 3.9 (3D): Phi = I_1 + I_2, I_1 by the zero-padded FFT,
                      I_2 over the ball of radius kmax (quad and kmax are then I_2's;
                      kmax = 0 and split_s = 0 select the defaults from tol and the box).
+    stretch          per-axis factors of the quadrature (k = S k', weights times det S) for
+                     anisotropic boxes; (1, 1, 1) is the plain rule.
     """
 
     def __init__(self, dim, n, L, dip_n=(0.0, 0.0, 1.0), dip_m=None, quad=(32, 16, 32), kmax=0.0,
-                 nyquist_mask=True, tol=1e-13, prec="fp64", kernel_width=0, split=False, split_s=0.0):
+                 nyquist_mask=True, tol=1e-13, prec="fp64", kernel_width=0, split=False, split_s=0.0,
+                 stretch=(1.0, 1.0, 1.0)):
         if prec not in ("fp64", "mixed"):
             raise ValueError("prec must be 'fp64' or 'mixed'")
         p = DDIParams()
@@ -132,6 +135,9 @@ class DDIPlan:
         p.kernel_width = int(kernel_width)
         p.split = 1 if split else 0
         p.split_s = float(split_s)
+        st = list(stretch) + [1.0] * (3 - len(stretch))
+        for i in range(3):
+            p.stretch[i] = float(st[i])
         self.dim = int(dim)
         self.shape = tuple(int(v) for v in n[:dim])
         self.L = tuple(float(v) for v in L[:dim])

@@ -51,7 +51,7 @@ class Params(ctypes.Structure):
                 ("n_rad", ctypes.c_int64), ("n_pol", ctypes.c_int64), ("n_azi", ctypes.c_int64),
                 ("kmax", ctypes.c_double), ("nyquist_mask", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("prec", ctypes.c_int32), ("kernel_width", ctypes.c_int32),
-                ("split", ctypes.c_int32), ("split_s", ctypes.c_double)]
+                ("split", ctypes.c_int32), ("split_s", ctypes.c_double), ("stretch", ctypes.c_double * 3)]
 
 
 def _params(**kw):
@@ -70,6 +70,8 @@ def _params(**kw):
     p.kernel_width = kw.get("kernel_width", 0)
     p.split = kw.get("split", 0)
     p.split_s = kw.get("split_s", 0.0)
+    for i, v in enumerate(kw.get("stretch", (1.0, 1.0, 1.0))):
+        p.stretch[i] = v
     return p
 
 
@@ -87,6 +89,7 @@ def _params(**kw):
     (dict(split=2), 1),
     (dict(split=1, split_s=float("inf")), 1),
     (dict(split=1, dim=2, n=(64, 64)), 4),    # the split is built for 3D only
+    (dict(stretch=(1.0, float("nan"), 1.0)), 1),
 ])
 def test_invalid_plans_are_rejected_before_device_use(lib, bad, code):
     lib.ddi_plan.argtypes = [ctypes.POINTER(Params), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
