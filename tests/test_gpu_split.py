@@ -64,6 +64,9 @@ CASES = [
     ((32, 32, 32), (8.0, 8.0, 8.0), (16, 16, 32), (0.0, 0.0, 1.0), None, 0.0, 0.0, "random"),
     ((16, 32, 64), (6.0, 8.0, 10.0), (12, 8, 16), (0.6, 0.0, 0.8), (0.0, 0.8, 0.6), 0.7, 3.0, "random"),
     ((64, 16, 16), (10.0, 5.0, 5.0), (8, 8, 8), (0.0, 1.0, 0.0), None, 0.0, 0.0, "random"),
+    # the largest axis (512 points: 1024-point padded transforms) along axis 0 and along the last axis
+    ((512, 16, 16), (32.0, 4.0, 4.0), (8, 8, 8), (0.6, 0.0, 0.8), None, 0.0, 0.0, "random"),
+    ((16, 16, 512), (4.0, 4.0, 32.0), (8, 8, 8), (0.0, 0.6, 0.8), None, 0.0, 0.0, "random"),
 ]
 
 
