@@ -500,7 +500,7 @@ def gf_step(phi_n: np.ndarray, prob: DDIProblem, gp: GPEParams, dt: float, n_inn
     return phi1 / norm
 
 
-def ts_step(psi_n: np.ndarray, prob: DDIProblem, gp: GPEParams, dt: float, delta: float = 0.0):
+def ts_step(psi_n: np.ndarray, prob: DDIProblem, gp: GPEParams, dt: float, delta: float = 0.0, q: float = 0.0):
     """One step of the second-order time splitting of Eq. tssp2 for the dipolar GPE of
     Eq. DipGPE1 with the cubic nonlinearity (sigma = 1), a time-independent dipole axis and the
     damping f = delta >= 0 (Case I: delta = 0; Case II: linear damping delta > 0):
@@ -513,11 +513,32 @@ def ts_step(psi_n: np.ndarray, prob: DDIProblem, gp: GPEParams, dt: float, delta
 
     (H, G, F are the Case I / Case II closed forms of Eqs. fun1-fun2 with h(phi, s) =
     phi exp(-2 delta s).)  The DFT is numpy's FFT (a library step); A is ddi_apply.
+
+    q > 0 (with delta > 0): Case III, the loss f(rho) = delta rho^q, whose closed forms for
+    sigma = 1 share one function of rho1,
+        w = [(1 + 2 q delta dt rho1^q)^(1 - 1/q) - 1] / (2 delta (q - 1) rho1^(q-1))   (q != 1)
+        w = ln(1 + 2 delta dt rho1) / (2 delta)                                          (q = 1)
+    with H = beta w, G = lam (A w), F = ln(1 + 2 q delta dt rho1^q) / (2 q).
     """
     psi = np.asarray(psi_n, dtype=np.complex128)
     kin = np.exp(-0.25j * dt * fourier_mu2(prob))
     psi1 = np.fft.ifftn(kin * np.fft.fftn(psi))
     rho1 = psi1.real ** 2 + psi1.imag ** 2
+    if q > 0.0:
+        if not delta > 0.0:
+            raise ValueError("Case III needs delta > 0")
+        x = 2.0 * q * delta * dt * rho1 ** q
+        if q == 1.0:
+            w = np.log1p(x) / (2.0 * delta)
+        else:
+            with np.errstate(divide="ignore", invalid="ignore"):
+                w = np.expm1((1.0 - 1.0 / q) * np.log1p(x)) / (2.0 * delta * (q - 1.0) * rho1 ** (q - 1.0))
+            w = np.where(rho1 > 0.0, w, 0.0)
+        theta = dt * trap_potential(prob, gp) + gp.beta * w
+        if gp.lam != 0.0:
+            theta = theta + gp.lam * ddi_apply(w, prob)
+        psi2 = psi1 * np.exp(-1j * theta) * np.exp(-np.log1p(x) / (2.0 * q))
+        return np.fft.ifftn(kin * np.fft.fftn(psi2))
     s = dt if delta == 0.0 else -math.expm1(-2.0 * delta * dt) / (2.0 * delta)
     theta = dt * trap_potential(prob, gp) + gp.beta * s * rho1
     if gp.lam != 0.0:

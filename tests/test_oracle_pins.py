@@ -663,3 +663,37 @@ def test_stretched_quadrature_resolves_a_z_localized_gaussian():
         errs[st[2]] = float(np.max(np.abs(got - ex)) / np.max(np.abs(ex)))
     assert errs[1.0 / eps] < 2e-6, errs
     assert errs[1.0] > 1e-3, errs
+
+
+@pytest.mark.parametrize("q,delta", [(1.0, 4.0), (2.0, 20.0), (1.5, 8.0)])
+def test_time_splitting_case_iii_matches_ode_integration(q, delta):
+    """Case III (f(rho) = delta rho^q: two-body q = 1, three-body q = 2) against a fine RK4
+    integration of the nonlinear sub-problem i psi_t = (V + beta |psi|^2 + lam A|psi|^2
+    - i delta |psi|^(2q)) psi between the exact half kinetic steps.  delta is large enough that
+    the loss changes the mass by several per cent over the step."""
+    p, gp, psi = _ts_case()
+    dt = 0.05
+    kin = np.exp(-0.25j * dt * O.fourier_mu2(p))
+    V = O.trap_potential(p, gp)
+
+    def rhs(y):
+        r = np.abs(y) ** 2
+        return (-1j * (V + gp.beta * r + gp.lam * O.ddi_apply(r, p)) - delta * r ** q) * y
+
+    y = np.fft.ifftn(kin * np.fft.fftn(psi))
+    m = 100
+    h = dt / m
+    for _ in range(m):
+        k1 = rhs(y)
+        k2 = rhs(y + 0.5 * h * k1)
+        k3 = rhs(y + 0.5 * h * k2)
+        k4 = rhs(y + h * k3)
+        y = y + h / 6.0 * (k1 + 2 * k2 + 2 * k3 + k4)
+    ref = np.fft.ifftn(kin * np.fft.fftn(y))
+    got = O.ts_step(psi, p, gp, dt=dt, delta=delta, q=q)
+    assert np.max(np.abs(got - ref)) < 1e-9 * np.max(np.abs(ref))
+    lost = 1.0 - _mass(got, p) / _mass(psi, p)
+    assert 0.02 < lost < 0.5, lost
+    # delta -> 0: Case I
+    assert np.max(np.abs(O.ts_step(psi, p, gp, dt=dt, delta=1e-9, q=q) - O.ts_step(psi, p, gp, dt=dt))) \
+        < 1e-8 * np.max(np.abs(psi))
