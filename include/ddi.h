@@ -234,6 +234,18 @@ ddi_status gpe_ts_step(ddi_plan_t plan, const gpe_params* gp, double dt, double 
                        const void* psi_in_dev, void* psi_out_dev, void* stream);
 
 /*
+ * The same step with the particle loss f(rho) = delta rho^q (Sec. 4.1, Case III of Eqs.
+ * fun1-fun2; q = 1 two-body, q = 2 three-body), cubic nonlinearity, time-independent axis.  With
+ * rho1 = |psi1|^2 the closed forms share one function
+ *   w = [(1 + 2 q delta dt rho1^q)^(1 - 1/q) - 1] / (2 delta (q - 1) rho1^(q-1))   (q != 1),
+ *   w = ln(1 + 2 delta dt rho1) / (2 delta)                                           (q = 1),
+ * and psi2 = psi1 exp(-i [dt V + beta w + lambda (A w)]) (1 + 2 q delta dt rho1^q)^(-1/(2q)).
+ * dt > 0, delta > 0 and q > 0 (finite) are required.  Otherwise as gpe_ts_step.
+ */
+ddi_status gpe_ts_step_loss(ddi_plan_t plan, const gpe_params* gp, double dt, double delta, double q,
+                            const void* psi_in_dev, void* psi_out_dev, void* stream);
+
+/*
  * Per-kernel timing of ddi_apply (sign = +1) or ddi_apply_adjoint (sign = -1):
  * runs the operator `reps` times on `stream` with HIP events between its
  * kernels and writes the mean duration in milliseconds of each stage to

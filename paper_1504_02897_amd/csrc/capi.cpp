@@ -179,6 +179,20 @@ ddi_status ensure_gpe(ddi::DevicePlan& P) {
   return DDI_OK;
 }
 
+ddi_status ts_step_impl(ddi_plan_t plan, const gpe_params& gp, double dt, double delta, double q, const void* in,
+                        void* out, void* stream, const char* what) {
+  ddi::DevicePlan& P = plan->P;
+  ddi_status st = P.mixed ? ensure_gpe<float>(P) : ensure_gpe<double>(P);
+  if (st != DDI_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = P.mixed ? ddi::run_ts_step<float>(P, gp, dt, delta, q, static_cast<const ddi::Complex<float>*>(in),
+                                                   static_cast<ddi::Complex<float>*>(out), s)
+                         : ddi::run_ts_step<double>(P, gp, dt, delta, q, static_cast<const ddi::Complex<double>*>(in),
+                                                    static_cast<ddi::Complex<double>*>(out), s);
+  if (e != hipSuccess) return hip_fail(e, what);
+  return DDI_OK;
+}
+
 ddi_status check_plan(ddi_plan_t plan) {
   if (!plan) return fail(DDI_EINVAL, "plan is NULL");
   int dev = -1;
@@ -504,17 +518,18 @@ ddi_status gpe_ts_step(ddi_plan_t plan, const gpe_params* gp, double dt, double 
   if (!gp || !psi_in_dev || !psi_out_dev) return fail(DDI_EINVAL, "NULL argument");
   if (dt == 0.0 || !std::isfinite(dt)) return fail(DDI_EINVAL, "dt must be finite and non-zero");
   if (!(delta >= 0.0) || !std::isfinite(delta)) return fail(DDI_EINVAL, "delta must be finite and >= 0");
-  ddi::DevicePlan& P = plan->P;
-  st = P.mixed ? ensure_gpe<float>(P) : ensure_gpe<double>(P);
+  return ts_step_impl(plan, *gp, dt, delta, 0.0, psi_in_dev, psi_out_dev, stream, "gpe_ts_step launch");
+}
+
+ddi_status gpe_ts_step_loss(ddi_plan_t plan, const gpe_params* gp, double dt, double delta, double q,
+                            const void* psi_in_dev, void* psi_out_dev, void* stream) {
+  ddi_status st = check_plan(plan);
   if (st != DDI_OK) return st;
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  hipError_t e = P.mixed ? ddi::run_ts_step<float>(P, *gp, dt, delta, static_cast<const ddi::Complex<float>*>(psi_in_dev),
-                                                   static_cast<ddi::Complex<float>*>(psi_out_dev), s)
-                         : ddi::run_ts_step<double>(P, *gp, dt, delta,
-                                                    static_cast<const ddi::Complex<double>*>(psi_in_dev),
-                                                    static_cast<ddi::Complex<double>*>(psi_out_dev), s);
-  if (e != hipSuccess) return hip_fail(e, "gpe_ts_step launch");
-  return DDI_OK;
+  if (!gp || !psi_in_dev || !psi_out_dev) return fail(DDI_EINVAL, "NULL argument");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DDI_EINVAL, "dt must be finite and positive");
+  if (!(delta > 0.0) || !std::isfinite(delta)) return fail(DDI_EINVAL, "delta must be finite and > 0");
+  if (!(q > 0.0) || !std::isfinite(q)) return fail(DDI_EINVAL, "q must be finite and > 0");
+  return ts_step_impl(plan, *gp, dt, delta, q, psi_in_dev, psi_out_dev, stream, "gpe_ts_step_loss launch");
 }
 
 }  // extern "C"

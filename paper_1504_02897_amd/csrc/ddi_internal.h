@@ -288,8 +288,8 @@ template <typename T>
 hipError_t run_gf_step(DevicePlan& P, const gpe_params& gp, double dt, int n_inner, const Complex<T>* psi_in,
                        Complex<T>* psi_out, hipStream_t s);
 template <typename T>
-hipError_t run_ts_step(DevicePlan& P, const gpe_params& gp, double dt, double delta, const Complex<T>* psi_in,
-                       Complex<T>* psi_out, hipStream_t s);
+hipError_t run_ts_step(DevicePlan& P, const gpe_params& gp, double dt, double delta, double q,
+                       const Complex<T>* psi_in, Complex<T>* psi_out, hipStream_t s);
 template <typename T>
 int gpe_reduction_blocks(const DevicePlan& P);
 

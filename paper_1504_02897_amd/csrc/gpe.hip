@@ -280,7 +280,7 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_ts_potential(C<T>* __restrict__ x, const T* __restrict__ rho,
                                                       const T* __restrict__ phi, const T* __restrict__ Vext,
                                                       int64_t n, GridGeo G, double dt, double sfac, double beta,
-                                                      double lam, double damp) {
+                                                      double lam, double damp, double loss_q, double loss_c) {
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
     const double th = dt * trap_v(i, G, Vext) +
@@ -289,7 +289,31 @@ __global__ void __launch_bounds__(256) k_ts_potential(C<T>* __restrict__ x, cons
     sincos(th, &sn, &cs);
     const C<T> v = x[i];
     const double re = static_cast<double>(v.re), im = static_cast<double>(v.im);
-    x[i] = C<T>{static_cast<T>((re * cs + im * sn) * damp), static_cast<T>((im * cs - re * sn) * damp)};
+    double a = damp;
+    if (loss_q > 0.0) {
+      // Case III: exp(-F) = (1 + 2 q delta dt rho1^q)^(-1/(2q)), loss_c = 2 q delta dt
+      const double r = re * re + im * im;
+      a = exp(-log1p(loss_c * pow(r, loss_q)) / (2.0 * loss_q));
+    }
+    x[i] = C<T>{static_cast<T>((re * cs + im * sn) * a), static_cast<T>((im * cs - re * sn) * a)};
+  }
+}
+
+// Case III (loss f(rho) = delta rho^q): w(rho1), the time integral of the decaying density over
+// the step, which enters H = beta w and G = lam A w.  loss_c = 2 q delta dt.
+template <typename T>
+__global__ void __launch_bounds__(256) k_loss_w(const C<T>* __restrict__ psi, T* __restrict__ w, int64_t n,
+                                                double q, double delta, double loss_c) {
+  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const double re = static_cast<double>(psi[i].re), im = static_cast<double>(psi[i].im);
+    const double r = re * re + im * im;
+    double v = 0.0;
+    if (r > 0.0) {
+      const double l = log1p(loss_c * pow(r, q));
+      v = q == 1.0 ? l / (2.0 * delta) : expm1((1.0 - 1.0 / q) * l) / (2.0 * delta * (q - 1.0) * pow(r, q - 1.0));
+    }
+    w[i] = static_cast<T>(v);
   }
 }
 
@@ -423,11 +447,12 @@ hipError_t run_gf_step(DevicePlan& P, const gpe_params& gp, double dt, int n_inn
 
 
 // One step of the second-order time splitting (Eq. tssp2), cubic nonlinearity, time-independent
-// dipole axis, damping f = delta >= 0 (Case I: 0; Case II: linear): half kinetic step, the
-// nonlinear step with rho and Phi = A rho of the half-stepped state, half kinetic step.
+// dipole axis, damping f = delta >= 0 (Case I: 0; Case II: linear) or, with q > 0, the loss
+// f = delta rho^q (Case III): half kinetic step, the nonlinear step with rho (Case III: w(rho))
+// and Phi = A rho (A w) of the half-stepped state, half kinetic step.
 template <typename T>
-hipError_t run_ts_step(DevicePlan& P, const gpe_params& gp, double dt, double delta, const Complex<T>* psi_in,
-                       Complex<T>* psi_out, hipStream_t s) {
+hipError_t run_ts_step(DevicePlan& P, const gpe_params& gp, double dt, double delta, double q,
+                       const Complex<T>* psi_in, Complex<T>* psi_out, hipStream_t s) {
   const HostTables& H = P.H;
   const int64_t n = static_cast<int64_t>(H.N[0]) * H.N[1] * H.N[2];
   const GridGeo G = geo_of(H, gp);
@@ -435,8 +460,10 @@ hipError_t run_ts_step(DevicePlan& P, const gpe_params& gp, double dt, double de
   T* rho = reinterpret_cast<T*>(P.gpe_rho);
   T* phi = reinterpret_cast<T*>(P.gpe_phi);
   const T* Vext = reinterpret_cast<const T*>(gp.V_dev);
-  // Case II time factor (1 - exp(-2 delta dt)) / (2 delta), dt in Case I
-  const double sfac = delta == 0.0 ? dt : -std::expm1(-2.0 * delta * dt) / (2.0 * delta);
+  // Case II time factor (1 - exp(-2 delta dt)) / (2 delta), dt in Case I; Case III: w carries it
+  const bool loss = q > 0.0;
+  const double loss_c = 2.0 * q * delta * dt;
+  const double sfac = loss ? 1.0 : (delta == 0.0 ? dt : -std::expm1(-2.0 * delta * dt) / (2.0 * delta));
   if (psi_out != psi_in) {
     hipLaunchKernelGGL((k_copy<T>), dim3(ew_blocks(n)), dim3(256), 0, s, psi_in, psi_out, n);
     DDI_CHECK(hipGetLastError());
@@ -448,11 +475,13 @@ hipError_t run_ts_step(DevicePlan& P, const gpe_params& gp, double dt, double de
     return fft3_full<T, +1>(P, psi_out, s);
   };
   DDI_CHECK(half_kinetic());
-  hipLaunchKernelGGL((k_density<T>), dim3(ew_blocks(n)), dim3(256), 0, s, psi_out, rho, n);
+  if (loss) hipLaunchKernelGGL((k_loss_w<T>), dim3(ew_blocks(n)), dim3(256), 0, s, psi_out, rho, n, q, delta, loss_c);
+  else hipLaunchKernelGGL((k_density<T>), dim3(ew_blocks(n)), dim3(256), 0, s, psi_out, rho, n);
   DDI_CHECK(hipGetLastError());
   if (gp.lambda != 0.0) DDI_CHECK(run_ddi<T>(P, rho, phi, +1, s, nullptr));
   hipLaunchKernelGGL((k_ts_potential<T>), dim3(ew_blocks(n)), dim3(256), 0, s, psi_out, rho,
-                     gp.lambda != 0.0 ? phi : rho, Vext, n, G, dt, sfac, gp.beta, gp.lambda, std::exp(-delta * dt));
+                     gp.lambda != 0.0 ? phi : rho, Vext, n, G, dt, sfac, gp.beta, gp.lambda,
+                     loss ? 1.0 : std::exp(-delta * dt), loss ? q : 0.0, loss_c);
   DDI_CHECK(hipGetLastError());
   return half_kinetic();
 }
@@ -465,10 +494,10 @@ template hipError_t run_gf_step<double>(DevicePlan&, const gpe_params&, double, 
                                         Complex<double>*, hipStream_t);
 template hipError_t run_gf_step<float>(DevicePlan&, const gpe_params&, double, int, const Complex<float>*,
                                        Complex<float>*, hipStream_t);
-template hipError_t run_ts_step<double>(DevicePlan&, const gpe_params&, double, double, const Complex<double>*,
-                                        Complex<double>*, hipStream_t);
-template hipError_t run_ts_step<float>(DevicePlan&, const gpe_params&, double, double, const Complex<float>*,
-                                       Complex<float>*, hipStream_t);
+template hipError_t run_ts_step<double>(DevicePlan&, const gpe_params&, double, double, double,
+                                        const Complex<double>*, Complex<double>*, hipStream_t);
+template hipError_t run_ts_step<float>(DevicePlan&, const gpe_params&, double, double, double,
+                                       const Complex<float>*, Complex<float>*, hipStream_t);
 template int gpe_reduction_blocks<double>(const DevicePlan&);
 template int gpe_reduction_blocks<float>(const DevicePlan&);
 

@@ -53,7 +53,7 @@ class PlanInfo(ctypes.Structure):
 
 
 EXPORTED = ["ddi_plan", "ddi_apply", "ddi_apply_adjoint", "ddi_type2", "ddi_type1", "gpe_energy_grad",
-            "gpe_gf_step", "gpe_ts_step", "ddi_set_dipole", "ddi_profile_apply", "ddi_plan_info", "ddi_plan_nodes", "ddi_destroy", "ddi_last_error"]
+            "gpe_gf_step", "gpe_ts_step", "gpe_ts_step_loss", "ddi_set_dipole", "ddi_profile_apply", "ddi_plan_info", "ddi_plan_nodes", "ddi_destroy", "ddi_last_error"]
 STAGES = ["fft_last_pad", "fft_axis1_t2", "fft_axis0_t2", "interp", "spread", "spread_reduce", "fft_axis0_t1",
           "fft_axis1_t1", "fft_last_trunc"]
 
@@ -70,6 +70,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.gpe_gf_step.argtypes = [vp, ctypes.POINTER(GPEParamsC), f64, i32, vp, vp, vp]
     lib.gpe_ts_step.argtypes = [vp, ctypes.POINTER(GPEParamsC), f64, f64, vp, vp, vp]
     lib.ddi_set_dipole.argtypes = [vp, ctypes.POINTER(f64), ctypes.POINTER(f64), vp]
+    lib.gpe_ts_step_loss.argtypes = [vp, ctypes.POINTER(GPEParamsC), f64, f64, f64, vp, vp, vp]
     lib.ddi_profile_apply.argtypes = [vp, vp, vp, i32, i32, ctypes.POINTER(f64), vp]
     lib.ddi_plan_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
     lib.ddi_plan_nodes.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(f64), ctypes.POINTER(f64)]
@@ -262,6 +263,15 @@ class DDIPlan:
         out = torch.empty_like(psi) if out is None else self._grid(out, complex_=True, name="out")
         _check(_lib.gpe_ts_step(self._h, ctypes.byref(gp), float(dt), float(delta), _ptr(psi), _ptr(out),
                                 _stream()))
+        return out
+
+    def ts_step_loss(self, psi, beta, lam, gamma=(1.0, 1.0, 1.0), dt=0.001, delta=1.0, q=2.0, V=None, out=None):
+        """One time-splitting step with the loss f(rho) = delta rho^q (gpe_ts_step_loss)."""
+        psi = self._grid(psi, complex_=True, name="psi")
+        gp, V = self._gp(beta, lam, gamma, V)
+        out = torch.empty_like(psi) if out is None else self._grid(out, complex_=True, name="out")
+        _check(_lib.gpe_ts_step_loss(self._h, ctypes.byref(gp), float(dt), float(delta), float(q), _ptr(psi),
+                                     _ptr(out), _stream()))
         return out
 
     def set_dipole(self, dip_n, dip_m=None):

@@ -421,3 +421,36 @@ def test_stretched_quadrature_fp64_matches_oracle(dim):
     say(f"  rel Linf = {err:.3e}")
     assert err < FP64_TOL
     assert abs(plan.info["kmax"] - prob.kmax_value()) <= 1e-13 * prob.kmax_value()
+
+
+@pytest.mark.parametrize("q,delta", [(1.0, 4.0), (2.0, 20.0), (1.5, 8.0)])
+def test_ts_step_loss_fp64_matches_oracle(q, delta):
+    """Case III (loss f(rho) = delta rho^q) through gpe_ts_step_loss, three steps."""
+    say(f"case: ts loss step 16^3 fp64 q {q} delta {delta}")
+    plan, prob, _, gp = gpe_case()
+    psi = ts_state(prob.n, prob.L)
+    x = to_dev(psi, torch.complex128)
+    ref = psi
+    for _ in range(3):
+        plan.ts_step_loss(x, gp.beta, gp.lam, gp.gamma, dt=0.02, delta=delta, q=q, out=x)
+        ref = O.ts_step(ref, prob, gp, dt=0.02, delta=delta, q=q)
+    err = relinf(x.cpu().numpy(), ref)
+    say(f"  rel Linf = {err:.3e}")
+    assert err < FP64_TOL
+    with pytest.raises(DDIError):
+        plan.ts_step_loss(x, gp.beta, gp.lam, gp.gamma, dt=-0.02, delta=delta, q=q)
+    with pytest.raises(DDIError):
+        plan.ts_step_loss(x, gp.beta, gp.lam, gp.gamma, dt=0.02, delta=0.0, q=q)
+    with pytest.raises(DDIError):
+        plan.ts_step_loss(x, gp.beta, gp.lam, gp.gamma, dt=0.02, delta=delta, q=0.0)
+
+
+def test_ts_step_loss_mixed_matches_oracle():
+    say("case: ts loss step 16^3 mixed q 2")
+    plan, prob, _, gp = gpe_case(prec="mixed")
+    psi = ts_state(prob.n, prob.L).astype(np.complex64)
+    out = plan.ts_step_loss(to_dev(psi, torch.complex64), gp.beta, gp.lam, gp.gamma, dt=0.02, delta=20.0, q=2.0)
+    ref = O.ts_step(psi.astype(np.complex128), prob, gp, dt=0.02, delta=20.0, q=2.0)
+    err = relinf(out.cpu().numpy().astype(np.complex128), ref)
+    say(f"  rel Linf = {err:.3e}")
+    assert err < MIXED_TOL
