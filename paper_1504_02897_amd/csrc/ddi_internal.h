@@ -37,6 +37,11 @@ constexpr int kSpreadBatch = DDI_SPREAD_BATCH;
 // the matrix-core kernels take longer chunks (cheaper per node)
 constexpr int kSpreadChunk = DDI_SPREAD_CHUNK;
 constexpr int kSpreadChunkMfma = DDI_SPREAD_CHUNK_MFMA;
+#ifndef DDI_SPREAD_WAVES
+#define DDI_SPREAD_WAVES 4096
+#endif
+// matrix-core chunks are shortened until the entries fill about this many items (resident waves)
+constexpr int kSpreadWaves = DDI_SPREAD_WAVES;
 #ifndef DDI_SPREAD_XCD_ORDER
 #define DDI_SPREAD_XCD_ORDER 0
 #endif

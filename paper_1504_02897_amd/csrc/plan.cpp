@@ -245,7 +245,7 @@ std::string build_spread_schedule(const HostTables& t, const std::vector<int64_t
   // ball of nodes crowds a few tiles, and one wave per long chunk then sets the duration)
   int chunk = kSpreadChunk;
   if (t.row_windows && kSpreadMfma) {
-    const int64_t per_wave = (count[ntile_total] + 4095) / 4096;
+    const int64_t per_wave = (count[ntile_total] + kSpreadWaves - 1) / kSpreadWaves;
     chunk = static_cast<int>(std::min<int64_t>(kSpreadChunkMfma, std::max<int64_t>(32, (per_wave + 15) / 16 * 16)));
   }
   S.items.clear();
