@@ -311,6 +311,22 @@ def other_workloads(args, torch, np, I, DDIPlan):
                     "dt=0.001, 100 steps, FP64",
         "steps": n_ts, "ms_per_step": round(1000.0 * el / n_ts, 3),
         "mass_rel_change": m1 / m0 - 1.0, "energy_rel_change": E1 / E0 - 1.0}
+
+    # the same dynamics with three-body loss (Case III, f = delta rho^2, delta = 3.512 as in the
+    # paper's collapse example)
+    print("[bench] c6_ts_loss", file=sys.stderr, flush=True)
+    x.copy_(psi)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n_ts):
+        p.ts_step_loss(x, wl["beta"], wl["lam"], g2, dt=dt_ts, delta=3.512, q=2.0, out=x)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    m2 = cell * float((x.abs() ** 2).sum())
+    res["c6_time_splitting_loss"] = {
+        "workload": "as c6_ts with the three-body loss f(rho) = 3.512 rho^2 (Case III, gpe_ts_step_loss), "
+                    "dt=0.001, 100 steps, FP64",
+        "steps": n_ts, "ms_per_step": round(1000.0 * el / n_ts, 3), "mass_rel_change": m2 / m0 - 1.0}
     del p, psi, x
 
     # the paper's Table 7, row lambda = beta = 207.16: ground state with converged inner solves
