@@ -93,8 +93,8 @@ typedef enum { DDI_FP64 = 0, DDI_MIXED = 1 } ddi_precision;
  *                 I_2 = the quadrature sum above over the ball of radius kmax
  *                       with every weight c_q multiplied by q(k_q).
  *               The quadrature sizes and kmax are then those of I_2, and
- *               kmax <= 0 selects s sqrt(ln(1/tol)).  ddi_type2 / ddi_type1
- *               act on the I_2 nodes.
+ *               kmax <= 0 selects s sqrt(ln(1/tol)) (divided by the smallest
+ *               stretch factor).  ddi_type2 / ddi_type1 act on the I_2 nodes.
  *  split_s      s of the partition (split = 1); <= 0 selects
  *               sqrt(ln(1/tol)) / min_i L_i, which puts the decay
  *               exp(-s^2 r^2/4) of the short-range kernel at tol at the
