@@ -162,6 +162,19 @@ def test_zero_density_gives_zero():
     assert float(phi.abs().max()) == 0.0
 
 
+def test_nan_input_propagates():
+    """NaN or Inf inputs are not trapped (the header says so): the call succeeds and the output
+    carries NaN; a later call on the same plan with clean input is clean again."""
+    say("case: NaN input")
+    p = DDIPlan(3, (16, 16, 16), (6.0,) * 3, dip_n=(0.6, 0, 0.8), quad=(8, 4, 8))
+    rho = torch.rand((16, 16, 16), dtype=torch.float64, device=DEV)
+    bad = rho.clone()
+    bad[3, 4, 5] = float("nan")
+    assert bool(torch.isnan(p.apply(bad)).any())
+    clean = p.apply(rho)
+    assert bool(torch.isfinite(clean).all())
+
+
 def test_no_node_inside_box_is_an_error():
     """kmax far below the grid's Nyquist limit keeps every node; a tiny box with huge kmax too -
     but a plan whose nodes all fall outside the mask must be rejected."""
