@@ -73,6 +73,22 @@ KERNELS = {"fft_last_pad": "k_fft_contig (R2C_PAD)", "fft_axis1_t2": "k_fft_stri
            "fft_axis1_t1": "k_fft_strided (axis 1)", "fft_last_trunc": "k_fft_contig (C2R_TRUNC)"}
 
 
+def operator_model(plan, real_bytes, cplx_bytes, ms):
+    """Whole-operator HBM bound: every FFT pass sweeping the whole fine grid (read + write), two
+    transforms of d passes, plus reading rho and writing Phi; the rate it allows at 8 TB/s."""
+    nf = [v for v in plan.info["n_fine"] if v > 1]
+    d = len(nf)
+    nfine = 1
+    for v in nf:
+        nfine *= v
+    ngrid = 1
+    for v in plan.shape:
+        ngrid *= v
+    B = 2 * d * 2 * nfine * cplx_bytes + 2 * ngrid * real_bytes
+    bound = HBM_PEAK_GBS * 1e9 / B
+    return {"bytes": B, "bound_evals_s": round(bound, 1), "frac": round((1000.0 / ms) / bound, 4)}
+
+
 def roofline_of(stage, ms, model, fp_peak_tflops):
     """Roofline of one stage.  The binding roof is the larger of the two model times,
     B/HBM-peak and F/VALU-peak; `frac` is that roof's time over the measured time."""
@@ -480,6 +496,7 @@ def main():
     roof32["stages_ms"] = {k: round(v, 4) for k, v in stages32.items()}
 
     width32 = p32.info["width"]
+    opm32 = operator_model(p32, 4, 8, ms32)
     del p32, rho32, phi32, adj32
     extra = {}
     if not args.headline_only:
@@ -511,8 +528,10 @@ def main():
         "fwd_adj_ms": round(fa64, 4),
         "mixed": {"value": round(1000.0 / ms32, 3), "unit": "evals/s", "ms_per_step": round(ms32, 4),
                   "fwd_adj_ms": round(fa32, 4), "rel_linf_vs_fp64": err_mixed,
-                  "kernel_width": width32, "roofline": roof32},
+                  "kernel_width": width32, "roofline": roof32,
+                  "operator_model": opm32},
         "roofline": roof,
+        "operator_model": operator_model(p64, 8, 16, ms64),
         "cpu_baseline": cpu,
     }
     line.update(extra)
