@@ -302,6 +302,24 @@ def other_workloads(args, torch, np, I, DDIPlan):
         "energy_history": [[h[0], round(h[5], 8), round(h[7], 6)] for h in hist],
         "E_final": [float(v) for v in E], "energy_grad_ms": round(fa, 3)}
 
+    # the same flow in mixed precision (FP32 grids, FP64 tables and reductions)
+    print("[bench] c5_gf mixed", file=sys.stderr, flush=True)
+    q = DDIPlan(3, wl["n"], wl["L"], dip_n=(0.0, 0.0, 1.0), quad=wl["quad"], tol=1e-7, prec="mixed")
+    psi0m = torch.from_numpy(I.gf_initial(wl["n"], wl["L"], wl["gamma"])).cuda().to(torch.complex64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    psi_m, _ = ground_state(q, psi0m, wl["beta"], wl["lam"], wl["gamma"], dt=wl["dt"], steps=wl["steps"],
+                            energy_every=wl["steps"])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    Em, _ = q.energy_grad(psi_m, wl["beta"], wl["lam"], wl["gamma"], grad=False)
+    res["c5_gradient_flow_mixed"] = {
+        "workload": "c5_gf in mixed precision (FP32 grids, FP64 tables and reductions), same flow and steps",
+        "steps": wl["steps"], "ms_per_step": round(1000.0 * el / wl["steps"], 3),
+        "E_final": [float(v) for v in Em],
+        "E_parts_rel_diff_vs_fp64": [float(abs(a - b) / abs(b)) for a, b in zip(Em, E)]}
+    del q, psi_m, psi0m
+
     # the same flow on a split plan (Eq. 3.9; I_2 on 32x32x64 nodes)
     print("[bench] c5_gf split", file=sys.stderr, flush=True)
     q = DDIPlan(3, wl["n"], wl["L"], dip_n=(0.0, 0.0, 1.0), quad=(32, 32, 64), tol=wl["tol"], prec="fp64",
