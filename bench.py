@@ -287,6 +287,7 @@ def other_workloads(args, torch, np, I, DDIPlan):
     print(f"[bench] {name}", file=sys.stderr, flush=True)
     p = DDIPlan(3, wl["n"], wl["L"], dip_n=(0.0, 0.0, 1.0), quad=wl["quad"], tol=wl["tol"], prec="fp64")
     psi0 = torch.from_numpy(I.gf_initial(wl["n"], wl["L"], wl["gamma"])).cuda()
+    p.energy_grad(psi0, wl["beta"], wl["lam"], wl["gamma"], grad=False)   # the GPE workspace, outside the clock
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     psi, hist = ground_state(p, psi0, wl["beta"], wl["lam"], wl["gamma"], dt=wl["dt"], steps=wl["steps"],
@@ -306,6 +307,7 @@ def other_workloads(args, torch, np, I, DDIPlan):
     print("[bench] c5_gf mixed", file=sys.stderr, flush=True)
     q = DDIPlan(3, wl["n"], wl["L"], dip_n=(0.0, 0.0, 1.0), quad=wl["quad"], tol=1e-7, prec="mixed")
     psi0m = torch.from_numpy(I.gf_initial(wl["n"], wl["L"], wl["gamma"])).cuda().to(torch.complex64)
+    q.energy_grad(psi0m, wl["beta"], wl["lam"], wl["gamma"], grad=False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     psi_m, _ = ground_state(q, psi0m, wl["beta"], wl["lam"], wl["gamma"], dt=wl["dt"], steps=wl["steps"],
@@ -324,9 +326,10 @@ def other_workloads(args, torch, np, I, DDIPlan):
     print("[bench] c5_gf split", file=sys.stderr, flush=True)
     q = DDIPlan(3, wl["n"], wl["L"], dip_n=(0.0, 0.0, 1.0), quad=(32, 32, 64), tol=wl["tol"], prec="fp64",
                 split=True)
+    psi0s = torch.from_numpy(I.gf_initial(wl["n"], wl["L"], wl["gamma"])).cuda()   # the flow reuses its input
+    q.energy_grad(psi0s, wl["beta"], wl["lam"], wl["gamma"], grad=False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    psi0s = torch.from_numpy(I.gf_initial(wl["n"], wl["L"], wl["gamma"])).cuda()   # the flow reuses its input
     psi_s, _ = ground_state(q, psi0s, wl["beta"], wl["lam"], wl["gamma"], dt=wl["dt"], steps=wl["steps"],
                             energy_every=wl["steps"])
     torch.cuda.synchronize()
