@@ -84,6 +84,29 @@ __device__ __forceinline__ void block_sum4(double v[4], double* __restrict__ red
   }
 }
 
+// Combines slot j of the nblocks block partials red[b*4 + j] across one workgroup (a multiple of
+// 64 threads, at most kRedThreads), in a fixed order: thread t takes b = t, t + blockDim.x, ...;
+// then a butterfly within each wave and the waves in order.  Every thread returns the same value.
+template <typename Op>
+__device__ __forceinline__ double reduce_partials(const double* __restrict__ red, int nblocks, int j, double init,
+                                                  Op op) {
+  __shared__ double sh[kRedThreads / 64];
+  double v = init;
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) v = op(v, red[b * 4 + j]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = op(v, __shfl_xor(v, off, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = init;
+  for (int w = 0; w < static_cast<int>(blockDim.x) / 64; ++w) r = op(r, sh[w]);
+  __syncthreads();   // sh may be reused by the next call
+  return r;
+}
+
+struct OpSum { __device__ double operator()(double a, double b) const { return a + b; } };
+struct OpMax { __device__ double operator()(double a, double b) const { return fmax(a, b); } };
+struct OpMin { __device__ double operator()(double a, double b) const { return fmin(a, b); } };
+
 // sums of mu^2 |psihat|^2 (slot 0); also writes lap = 1/2 mu^2 psihat / prod(N) in place
 template <typename T>
 __global__ void __launch_bounds__(kRedThreads) k_kinetic(C<T>* __restrict__ ph, int64_t n, GridGeo G,
@@ -119,14 +142,10 @@ __global__ void __launch_bounds__(kRedThreads) k_energy_terms(const T* __restric
 // E_out[0..4] from the block partials (fixed order -> deterministic)
 __global__ void k_energy_final(const double* __restrict__ red_kin, const double* __restrict__ red_terms, int nblocks,
                                double cell, double inv_ntot, double beta, double lam, double* __restrict__ E) {
+  double s[4];
+  s[0] = reduce_partials(red_kin, nblocks, 0, 0.0, OpSum());
+  for (int j = 1; j < 4; ++j) s[j] = reduce_partials(red_terms, nblocks, j, 0.0, OpSum());
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double s[4] = {0, 0, 0, 0};
-  for (int b = 0; b < nblocks; ++b) {
-    s[0] += red_kin[b * 4 + 0];
-    s[1] += red_terms[b * 4 + 1];
-    s[2] += red_terms[b * 4 + 2];
-    s[3] += red_terms[b * 4 + 3];
-  }
   E[0] = 0.5 * cell * inv_ntot * s[0];
   E[1] = cell * s[1];
   E[2] = 0.5 * beta * cell * s[2];
@@ -184,9 +203,9 @@ __global__ void __launch_bounds__(kRedThreads) k_gf_coeff(const T* __restrict__ 
 
 // scal[0] = alpha = (max + min)/2
 __global__ void k_gf_alpha(const double* __restrict__ red, int nblocks, double* __restrict__ scal) {
+  const double mx = reduce_partials(red, nblocks, 0, -1e300, OpMax());
+  const double mn = reduce_partials(red, nblocks, 1, 1e300, OpMin());
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double mx = -1e300, mn = 1e300;
-  for (int b = 0; b < nblocks; ++b) { mx = fmax(mx, red[b * 4]); mn = fmin(mn, red[b * 4 + 1]); }
   scal[0] = 0.5 * (mx + mn);
 }
 
@@ -245,13 +264,7 @@ __global__ void __launch_bounds__(kRedThreads) k_norm2(const C<T>* __restrict__ 
 template <typename T>
 __global__ void __launch_bounds__(256) k_normalise(C<T>* __restrict__ x, int64_t n, const double* __restrict__ red,
                                                    int nblocks, double cell) {
-  __shared__ double f;
-  if (threadIdx.x == 0) {
-    double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += red[b * 4];
-    f = 1.0 / sqrt(cell * s);
-  }
-  __syncthreads();
+  const double f = 1.0 / sqrt(cell * reduce_partials(red, nblocks, 0, 0.0, OpSum()));
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
     const C<T> p = x[i];
@@ -382,7 +395,7 @@ hipError_t run_gpe_energy_grad(DevicePlan& P, const gpe_params& gp, const Comple
   DDI_CHECK(hipGetLastError());
   hipLaunchKernelGGL((k_energy_terms<T>), dim3(nb), dim3(kRedThreads), 0, s, rho, phi, Vext, n, G, red_terms);
   DDI_CHECK(hipGetLastError());
-  hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(64), 0, s, red_kin, red_terms, nb, H.cell, inv_ntot, gp.beta,
+  hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(kRedThreads), 0, s, red_kin, red_terms, nb, H.cell, inv_ntot, gp.beta,
                      gp.lambda, E_dev);
   DDI_CHECK(hipGetLastError());
   if (grad) {
@@ -417,7 +430,7 @@ hipError_t run_gf_step(DevicePlan& P, const gpe_params& gp, double dt, int n_inn
   hipLaunchKernelGGL((k_gf_coeff<T>), dim3(nb), dim3(kRedThreads), 0, s, rho, phi, Vext, n, G, gp.beta, gp.lambda,
                      Bc, red);
   DDI_CHECK(hipGetLastError());
-  hipLaunchKernelGGL(k_gf_alpha, dim3(1), dim3(64), 0, s, red, nb, scal);
+  hipLaunchKernelGGL(k_gf_alpha, dim3(1), dim3(kRedThreads), 0, s, red, nb, scal);
   DDI_CHECK(hipGetLastError());
   // rhs0 = FFT(psi_in) / dt
   hipLaunchKernelGGL((k_copy<T>), dim3(ew_blocks(n)), dim3(256), 0, s, psi_in, rhs0, n);
