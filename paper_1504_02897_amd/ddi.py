@@ -100,6 +100,35 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def make_params(dim, n, L, dip_n=(0.0, 0.0, 1.0), dip_m=None, quad=(32, 16, 32), kmax=0.0,
+                nyquist_mask=True, tol=1e-13, prec="fp64", kernel_width=0, split=False, split_s=0.0,
+                stretch=(1.0, 1.0, 1.0)) -> DDIParams:
+    """The ddi_params struct of a plan; the arguments are those of DDIPlan."""
+    if prec not in ("fp64", "mixed"):
+        raise ValueError("prec must be 'fp64' or 'mixed'")
+    p = DDIParams()
+    p.dim = int(dim)
+    nn = list(n) + [1] * (3 - len(n))
+    LL = list(L) + [1.0] * (3 - len(L))
+    for i in range(3):
+        p.n[i] = int(nn[i])
+        p.L[i] = float(LL[i])
+        p.dip_n[i] = float(dip_n[i])
+        p.dip_m[i] = 0.0 if dip_m is None else float(dip_m[i])
+    p.n_rad, p.n_pol, p.n_azi = (int(quad[0]), int(quad[1]), int(quad[2]))
+    p.kmax = float(kmax)
+    p.nyquist_mask = 1 if nyquist_mask else 0
+    p.tol = float(tol)
+    p.prec = DDI_MIXED if prec == "mixed" else DDI_FP64
+    p.kernel_width = int(kernel_width)
+    p.split = 1 if split else 0
+    p.split_s = float(split_s)
+    st = list(stretch) + [1.0] * (3 - len(stretch))
+    for i in range(3):
+        p.stretch[i] = float(st[i])
+    return p
+
+
 class DDIPlan:
     """A DDI plan: quadrature, kernel tables, spread schedule and workspace on one GPU.
 
@@ -117,28 +146,8 @@ class DDIPlan:
     def __init__(self, dim, n, L, dip_n=(0.0, 0.0, 1.0), dip_m=None, quad=(32, 16, 32), kmax=0.0,
                  nyquist_mask=True, tol=1e-13, prec="fp64", kernel_width=0, split=False, split_s=0.0,
                  stretch=(1.0, 1.0, 1.0)):
-        if prec not in ("fp64", "mixed"):
-            raise ValueError("prec must be 'fp64' or 'mixed'")
-        p = DDIParams()
-        p.dim = int(dim)
-        nn = list(n) + [1] * (3 - len(n))
-        LL = list(L) + [1.0] * (3 - len(L))
-        for i in range(3):
-            p.n[i] = int(nn[i])
-            p.L[i] = float(LL[i])
-            p.dip_n[i] = float(dip_n[i])
-            p.dip_m[i] = 0.0 if dip_m is None else float(dip_m[i])
-        p.n_rad, p.n_pol, p.n_azi = (int(quad[0]), int(quad[1]), int(quad[2]))
-        p.kmax = float(kmax)
-        p.nyquist_mask = 1 if nyquist_mask else 0
-        p.tol = float(tol)
-        p.prec = DDI_MIXED if prec == "mixed" else DDI_FP64
-        p.kernel_width = int(kernel_width)
-        p.split = 1 if split else 0
-        p.split_s = float(split_s)
-        st = list(stretch) + [1.0] * (3 - len(stretch))
-        for i in range(3):
-            p.stretch[i] = float(st[i])
+        p = make_params(dim, n, L, dip_n, dip_m, quad, kmax, nyquist_mask, tol, prec, kernel_width,
+                        split, split_s, stretch)
         self.dim = int(dim)
         self.shape = tuple(int(v) for v in n[:dim])
         self.L = tuple(float(v) for v in L[:dim])
