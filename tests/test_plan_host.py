@@ -280,6 +280,23 @@ def test_schedules_cover_every_support_once(tables, name, which):
     assert np.array_equal(cov, used.astype(np.int64))
 
 
+def test_twiddle_tables_are_the_roots_of_unity(tables):
+    """twiddle_table(n)[k] = exp(-2 pi i k / n) within one ulp (reference: 40-digit mpmath); the
+    exact zeros come out of the long-double angle within 2e-19."""
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 40
+    t = tables["3d_fp64"]
+    for n in (4, 64, 256, 1024):
+        tw = t[f"twiddle{n}"]
+        assert tw.size == 2 * n
+        ang = [2 * mp.pi * k / n for k in range(n)]
+        re = np.array([float(mp.cos(x)) for x in ang])
+        im = np.array([float(-mp.sin(x)) for x in ang])
+        ulp = lambda v: np.maximum(np.spacing(np.abs(v)), 2.5e-19)
+        assert np.all(np.abs(tw[0::2] - re) <= ulp(re))
+        assert np.all(np.abs(tw[1::2] - im) <= ulp(im))
+
+
 def test_rejected_parameters_report_an_error(driver, tmp_path):
     t = run_tables(driver, tmp_path, dim=3, n=(48, 32, 32), L=(8.0,) * 3)
     assert int(t["status"][0]) != 0
