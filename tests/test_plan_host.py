@@ -78,6 +78,9 @@ CASES = {
     "3d_split": (dict(dim=3, n=(32, 32, 32), L=(8.0,) * 3, dip_n=(0.0, 0.6, 0.8), quad=(16, 16, 32), tol=1e-13,
                       split=True),
                  dict(dim=3, n=(32, 32, 32), L=(8.0,) * 3, dip_n=(0.0, 0.6, 0.8), n_rad=16, n_pol=16, n_azi=32)),
+    # a small ball whose supports end on the last position of a tile: the axis-1 window is tight
+    "3d_split_64": (dict(dim=3, n=(64, 64, 64), L=(8.0,) * 3, quad=(12, 12, 24), tol=1e-13, split=True, split_s=1.5),
+                    dict(dim=3, n=(64, 64, 64), L=(8.0,) * 3, n_rad=12, n_pol=12, n_azi=24)),
 }
 
 
