@@ -224,6 +224,34 @@ def split_workload(args, torch, np, I, DDIPlan):
     return split
 
 
+def gf_workload(args, torch, np, I, DDIPlan):
+    """The FP64 gradient flow to the ground state at 128^3 (Sec. 3.1): 200 steps, each one DDI
+    evaluation; returns the plan, the initial state, the ground state, its energy parts and the
+    result record."""
+    from paper_1504_02897_amd.gf import ground_state
+
+    name = "c5_gf"
+    wl = I.WORKLOADS[name]
+    print(f"[bench] {name}", file=sys.stderr, flush=True)
+    p = DDIPlan(3, wl["n"], wl["L"], dip_n=(0.0, 0.0, 1.0), quad=wl["quad"], tol=wl["tol"], prec="fp64")
+    psi0 = torch.from_numpy(I.gf_initial(wl["n"], wl["L"], wl["gamma"])).cuda()
+    p.energy_grad(psi0, wl["beta"], wl["lam"], wl["gamma"], grad=False)   # the GPE workspace, outside the clock
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    psi, hist = ground_state(p, psi0, wl["beta"], wl["lam"], wl["gamma"], dt=wl["dt"], steps=wl["steps"],
+                             energy_every=50)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    E, G = p.energy_grad(psi, wl["beta"], wl["lam"], wl["gamma"], grad=True)
+    fa = time_steps(lambda: p.energy_grad(psi, wl["beta"], wl["lam"], wl["gamma"], grad=True), 5, 1, torch)
+    return p, psi0, psi, E, {
+        "workload": "c5_gf: 3D dipolar GPE ground state by gradient flow, 128^3 on [-8,8)^3, "
+                    "V=(x^2+y^2+25z^2)/2, beta=200, lambda=150, n=z, dt=0.01, 200 steps, FP64",
+        "steps": wl["steps"], "ms_per_step": round(1000.0 * el / wl["steps"], 3),
+        "energy_history": [[h[0], round(h[5], 8), round(h[7], 6)] for h in hist],
+        "E_final": [float(v) for v in E], "energy_grad_ms": round(fa, 3)}
+
+
 def other_workloads(args, torch, np, I, DDIPlan):
     """The remaining workloads, each timed on its own plan: the split of Eq. 3.9 on the c2_128 input,
     quasi-2D 512^2 FP64 (c3_512), 3D 256^3 mixed (c4_256) and the 128^3 ground-state gradient flow
@@ -284,24 +312,7 @@ def other_workloads(args, torch, np, I, DDIPlan):
 
     name = "c5_gf"
     wl = I.WORKLOADS[name]
-    print(f"[bench] {name}", file=sys.stderr, flush=True)
-    p = DDIPlan(3, wl["n"], wl["L"], dip_n=(0.0, 0.0, 1.0), quad=wl["quad"], tol=wl["tol"], prec="fp64")
-    psi0 = torch.from_numpy(I.gf_initial(wl["n"], wl["L"], wl["gamma"])).cuda()
-    p.energy_grad(psi0, wl["beta"], wl["lam"], wl["gamma"], grad=False)   # the GPE workspace, outside the clock
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    psi, hist = ground_state(p, psi0, wl["beta"], wl["lam"], wl["gamma"], dt=wl["dt"], steps=wl["steps"],
-                             energy_every=50)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    E, G = p.energy_grad(psi, wl["beta"], wl["lam"], wl["gamma"], grad=True)
-    fa = time_steps(lambda: p.energy_grad(psi, wl["beta"], wl["lam"], wl["gamma"], grad=True), 5, 1, torch)
-    res["c5_gradient_flow"] = {
-        "workload": "c5_gf: 3D dipolar GPE ground state by gradient flow, 128^3 on [-8,8)^3, "
-                    "V=(x^2+y^2+25z^2)/2, beta=200, lambda=150, n=z, dt=0.01, 200 steps, FP64",
-        "steps": wl["steps"], "ms_per_step": round(1000.0 * el / wl["steps"], 3),
-        "energy_history": [[h[0], round(h[5], 8), round(h[7], 6)] for h in hist],
-        "E_final": [float(v) for v in E], "energy_grad_ms": round(fa, 3)}
+    p, psi0, psi, E, res["c5_gradient_flow"] = gf_workload(args, torch, np, I, DDIPlan)
 
     # the same flow in mixed precision (FP32 grids, FP64 tables and reductions)
     print("[bench] c5_gf mixed", file=sys.stderr, flush=True)
@@ -454,6 +465,8 @@ def main():
     ap.add_argument("--profile-reps", type=int, default=10)
     ap.add_argument("--headline-only", action="store_true",
                     help="skip the 2D, 256^3 mixed and gradient-flow workloads")
+    ap.add_argument("--gf-only", action="store_true",
+                    help="run only the FP64 gradient flow at 128^3 and print its record")
     ap.add_argument("--split-only", action="store_true",
                     help="time only the split of Eq. 3.9 on the c2_128 input and print its JSON object")
     args = ap.parse_args()
@@ -471,6 +484,9 @@ def main():
     torch.cuda.set_device(0)
     if args.split_only:
         print(json.dumps({"c2_split": split_workload(args, torch, np, I, DDIPlan)}), flush=True)
+        return
+    if args.gf_only:
+        print(json.dumps({"c5_gradient_flow": gf_workload(args, torch, np, I, DDIPlan)[4]}), flush=True)
         return
     name = "c2_128"
     wl = I.WORKLOADS[name]

@@ -211,9 +211,8 @@ __global__ void k_gf_alpha(const double* __restrict__ red, int nblocks, double* 
 
 // r = (alpha - B) phi
 template <typename T>
-__global__ void __launch_bounds__(256) k_gf_residual(const C<T>* __restrict__ phi, const T* __restrict__ B,
-                                                     const double* __restrict__ scal, int64_t n,
-                                                     C<T>* __restrict__ r) {
+__global__ void __launch_bounds__(256) k_gf_residual(const C<T>* phi, const T* __restrict__ B,
+                                                     const double* __restrict__ scal, int64_t n, C<T>* r) {
   const double alpha = scal[0];
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
@@ -229,22 +228,12 @@ __global__ void __launch_bounds__(256) k_gf_solve(C<T>* __restrict__ rh, const C
                                                   const double* __restrict__ scal, int64_t n, GridGeo G, double dt,
                                                   double inv_ntot) {
   const double alpha = scal[0];
+  const double inv_dt = 1.0 / dt;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const double den = (1.0 / dt + alpha + 0.5 * mu2_of(i, G)) / inv_ntot;
+    const double den = (inv_dt + alpha + 0.5 * mu2_of(i, G)) / inv_ntot;
     const C<T> a = rhs0[i], b = rh[i];
-    rh[i] = C<T>{static_cast<T>((static_cast<double>(a.re) + b.re) / den),
-                 static_cast<T>((static_cast<double>(a.im) + b.im) / den)};
-  }
-}
-
-// x <- x * f
-template <typename T>
-__global__ void __launch_bounds__(256) k_scale(C<T>* __restrict__ x, int64_t n, double f) {
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const C<T> p = x[i];
-    x[i] = C<T>{static_cast<T>(f * p.re), static_cast<T>(f * p.im)};
+    rh[i] = C<T>{static_cast<T>((inv_dt * a.re + b.re) / den), static_cast<T>((inv_dt * a.im + b.im) / den)};
   }
 }
 
@@ -260,15 +249,15 @@ __global__ void __launch_bounds__(kRedThreads) k_norm2(const C<T>* __restrict__ 
   block_sum4(v, red);
 }
 
-// x <- x / sqrt(cell * sum)
+// y <- x / sqrt(cell * sum) (y may be x)
 template <typename T>
-__global__ void __launch_bounds__(256) k_normalise(C<T>* __restrict__ x, int64_t n, const double* __restrict__ red,
+__global__ void __launch_bounds__(256) k_normalise(const C<T>* x, C<T>* y, int64_t n, const double* __restrict__ red,
                                                    int nblocks, double cell) {
   const double f = 1.0 / sqrt(cell * reduce_partials(red, nblocks, 0, 0.0, OpSum()));
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
     const C<T> p = x[i];
-    x[i] = C<T>{static_cast<T>(f * p.re), static_cast<T>(f * p.im)};
+    y[i] = C<T>{static_cast<T>(f * p.re), static_cast<T>(f * p.im)};
   }
 }
 
@@ -432,29 +421,24 @@ hipError_t run_gf_step(DevicePlan& P, const gpe_params& gp, double dt, int n_inn
   DDI_CHECK(hipGetLastError());
   hipLaunchKernelGGL(k_gf_alpha, dim3(1), dim3(kRedThreads), 0, s, red, nb, scal);
   DDI_CHECK(hipGetLastError());
-  // rhs0 = FFT(psi_in) / dt
+  // rhs0 = FFT(psi_in); k_gf_solve divides it by dt
   hipLaunchKernelGGL((k_copy<T>), dim3(ew_blocks(n)), dim3(256), 0, s, psi_in, rhs0, n);
   DDI_CHECK(hipGetLastError());
   DDI_CHECK((fft3_full<T, -1>(P, rhs0, s)));
-  hipLaunchKernelGGL((k_scale<T>), dim3(ew_blocks(n)), dim3(256), 0, s, rhs0, n, 1.0 / dt);
-  DDI_CHECK(hipGetLastError());
-  if (psi_out != psi_in) {
-    hipLaunchKernelGGL((k_copy<T>), dim3(ew_blocks(n)), dim3(256), 0, s, psi_in, psi_out, n);
-    DDI_CHECK(hipGetLastError());
-  }
+  // the iterate: psi_in, then r (updated in place); normalised into psi_out at the end
+  const Complex<T>* cur = psi_in;
   for (int it = 0; it < n_inner; ++it) {
-    hipLaunchKernelGGL((k_gf_residual<T>), dim3(ew_blocks(n)), dim3(256), 0, s, psi_out, Bc, scal, n, r);
+    hipLaunchKernelGGL((k_gf_residual<T>), dim3(ew_blocks(n)), dim3(256), 0, s, cur, Bc, scal, n, r);
     DDI_CHECK(hipGetLastError());
     DDI_CHECK((fft3_full<T, -1>(P, r, s)));
     hipLaunchKernelGGL((k_gf_solve<T>), dim3(ew_blocks(n)), dim3(256), 0, s, r, rhs0, scal, n, G, dt, inv_ntot);
     DDI_CHECK(hipGetLastError());
     DDI_CHECK((fft3_full<T, +1>(P, r, s)));
-    hipLaunchKernelGGL((k_copy<T>), dim3(ew_blocks(n)), dim3(256), 0, s, r, psi_out, n);
-    DDI_CHECK(hipGetLastError());
+    cur = r;
   }
-  hipLaunchKernelGGL((k_norm2<T>), dim3(nb), dim3(kRedThreads), 0, s, psi_out, n, red);
+  hipLaunchKernelGGL((k_norm2<T>), dim3(nb), dim3(kRedThreads), 0, s, cur, n, red);
   DDI_CHECK(hipGetLastError());
-  hipLaunchKernelGGL((k_normalise<T>), dim3(ew_blocks(n)), dim3(256), 0, s, psi_out, n, red, nb, H.cell);
+  hipLaunchKernelGGL((k_normalise<T>), dim3(ew_blocks(n)), dim3(256), 0, s, cur, psi_out, n, red, nb, H.cell);
   return hipGetLastError();
 }
 
