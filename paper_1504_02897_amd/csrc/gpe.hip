@@ -59,13 +59,6 @@ __global__ void __launch_bounds__(256) k_density(const C<T>* __restrict__ psi, T
   }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_copy(const C<T>* __restrict__ a, C<T>* __restrict__ b, int64_t n) {
-  for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
-       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
-    b[i] = a[i];
-}
-
 // Block-level FP64 sum of up to 4 values; partial sums to red[block*4 + j].
 __device__ __forceinline__ void block_sum4(double v[4], double* __restrict__ red) {
   __shared__ double sh[4][kRedThreads / 64];
@@ -338,12 +331,14 @@ int gpe_reduction_blocks(const DevicePlan& P) {
   return static_cast<int>(b);
 }
 
-// In-place complex 3D FFT of an unpadded N0 x N1 x N2 grid.
+// Complex 3D FFT of an unpadded N0 x N1 x N2 grid into X, in place, or from `in` when it is
+// given (the first pass reads it; `in` is not modified).
 template <typename T, int SIGN>
-static hipError_t fft3_full(DevicePlan& P, C<T>* X, hipStream_t s) {
+static hipError_t fft3_full(DevicePlan& P, C<T>* X, hipStream_t s, const C<T>* in = nullptr) {
   const HostTables& H = P.H;
   const C<T>* tw2 = reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.N[2])]);
-  DDI_CHECK((launch_contig<T, SIGN, C2C>(H.N[2], X, X, H.N[0], H.N[1], H.N[0], H.N[1], H.N[2], 0, H.N[2], nullptr,
+  const C<T>* src = in ? in : X;
+  DDI_CHECK((launch_contig<T, SIGN, C2C>(H.N[2], src, X, H.N[0], H.N[1], H.N[0], H.N[1], H.N[2], 0, H.N[2], nullptr,
                                          nullptr, nullptr, tw2, s)));
   DDI_CHECK((launch_strided<T, SIGN>(H.N[1], X, 1, H.N[0], H.N[1], H.N[2], H.N[0], 0, H.N[1], 0, 0, H.N[1], 0, H.N[2],
                                      reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.N[1])]), s)));
@@ -377,9 +372,7 @@ hipError_t run_gpe_energy_grad(DevicePlan& P, const gpe_params& gp, const Comple
   hipLaunchKernelGGL((k_density<T>), dim3(ew_blocks(n)), dim3(256), 0, s, psi, rho, n);
   DDI_CHECK(hipGetLastError());
   DDI_CHECK(run_ddi<T>(P, rho, phi, +1, s, nullptr));
-  hipLaunchKernelGGL((k_copy<T>), dim3(ew_blocks(n)), dim3(256), 0, s, psi, c1, n);
-  DDI_CHECK(hipGetLastError());
-  DDI_CHECK((fft3_full<T, -1>(P, c1, s)));
+  DDI_CHECK((fft3_full<T, -1>(P, c1, s, psi)));
   hipLaunchKernelGGL((k_kinetic<T>), dim3(nb), dim3(kRedThreads), 0, s, c1, n, G, inv_ntot, red_kin);
   DDI_CHECK(hipGetLastError());
   hipLaunchKernelGGL((k_energy_terms<T>), dim3(nb), dim3(kRedThreads), 0, s, rho, phi, Vext, n, G, red_terms);
@@ -422,9 +415,7 @@ hipError_t run_gf_step(DevicePlan& P, const gpe_params& gp, double dt, int n_inn
   hipLaunchKernelGGL(k_gf_alpha, dim3(1), dim3(kRedThreads), 0, s, red, nb, scal);
   DDI_CHECK(hipGetLastError());
   // rhs0 = FFT(psi_in); k_gf_solve divides it by dt
-  hipLaunchKernelGGL((k_copy<T>), dim3(ew_blocks(n)), dim3(256), 0, s, psi_in, rhs0, n);
-  DDI_CHECK(hipGetLastError());
-  DDI_CHECK((fft3_full<T, -1>(P, rhs0, s)));
+  DDI_CHECK((fft3_full<T, -1>(P, rhs0, s, psi_in)));
   // the iterate: psi_in, then r (updated in place); normalised into psi_out at the end
   const Complex<T>* cur = psi_in;
   for (int it = 0; it < n_inner; ++it) {
@@ -461,17 +452,14 @@ hipError_t run_ts_step(DevicePlan& P, const gpe_params& gp, double dt, double de
   const bool loss = q > 0.0;
   const double loss_c = 2.0 * q * delta * dt;
   const double sfac = loss ? 1.0 : (delta == 0.0 ? dt : -std::expm1(-2.0 * delta * dt) / (2.0 * delta));
-  if (psi_out != psi_in) {
-    hipLaunchKernelGGL((k_copy<T>), dim3(ew_blocks(n)), dim3(256), 0, s, psi_in, psi_out, n);
-    DDI_CHECK(hipGetLastError());
-  }
-  auto half_kinetic = [&]() -> hipError_t {
-    DDI_CHECK((fft3_full<T, -1>(P, psi_out, s)));
+  // the first transform reads psi_in; everything after it works in place on psi_out
+  auto half_kinetic = [&](const Complex<T>* from) -> hipError_t {
+    DDI_CHECK((fft3_full<T, -1>(P, psi_out, s, from)));
     hipLaunchKernelGGL((k_ts_kinetic<T>), dim3(ew_blocks(n)), dim3(256), 0, s, psi_out, n, G, 0.25 * dt, inv_ntot);
     DDI_CHECK(hipGetLastError());
     return fft3_full<T, +1>(P, psi_out, s);
   };
-  DDI_CHECK(half_kinetic());
+  DDI_CHECK(half_kinetic(psi_in));
   if (loss) hipLaunchKernelGGL((k_loss_w<T>), dim3(ew_blocks(n)), dim3(256), 0, s, psi_out, rho, n, q, delta, loss_c);
   else hipLaunchKernelGGL((k_density<T>), dim3(ew_blocks(n)), dim3(256), 0, s, psi_out, rho, n);
   DDI_CHECK(hipGetLastError());
@@ -480,7 +468,7 @@ hipError_t run_ts_step(DevicePlan& P, const gpe_params& gp, double dt, double de
                      gp.lambda != 0.0 ? phi : rho, Vext, n, G, dt, sfac, gp.beta, gp.lambda,
                      loss ? 1.0 : std::exp(-delta * dt), loss ? q : 0.0, loss_c);
   DDI_CHECK(hipGetLastError());
-  return half_kinetic();
+  return half_kinetic(psi_out);
 }
 
 template hipError_t run_gpe_energy_grad<double>(DevicePlan&, const gpe_params&, const Complex<double>*, double*,
