@@ -319,6 +319,23 @@ def test_gf_step_fp64_matches_oracle():
     assert relinf(out.cpu().numpy(), ref) < FP64_TOL
 
 
+def test_gf_step_fp64_in_place_and_without_inner_steps():
+    """out = input gives the out-of-place result; n_inner = 0 only normalises the input."""
+    say("case: gf step 16^3 fp64 in place, n_inner 2 and 0")
+    plan, prob, psi, gp = gpe_case()
+    x = to_dev(psi, torch.complex128)
+    sep = plan.gf_step(x, gp.beta, gp.lam, gp.gamma, dt=0.01, n_inner=2)
+    y = x.clone()
+    plan.gf_step(y, gp.beta, gp.lam, gp.gamma, dt=0.01, n_inner=2, out=y)
+    torch.cuda.synchronize()
+    assert torch.equal(sep, y)
+    assert torch.equal(x, to_dev(psi, torch.complex128))          # the input of the separate call is intact
+    assert relinf(y.cpu().numpy(), O.gf_step(psi, prob, gp, dt=0.01, n_inner=2)) < FP64_TOL
+    z = plan.gf_step(x, gp.beta, gp.lam, gp.gamma, dt=0.01, n_inner=0)
+    ref = psi / np.sqrt(prob.cell * np.sum(np.abs(psi) ** 2))
+    assert relinf(z.cpu().numpy(), ref) < 1e-14
+
+
 # ---------------------------------------------------------------- GPE dynamics: time splitting (Eq. tssp2)
 def ts_state(n, L):
     """A moving, asymmetric state (plane-wave phase times a skewed mixture), normalised."""
