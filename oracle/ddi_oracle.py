@@ -42,6 +42,7 @@ import math
 from dataclasses import dataclass, field
 
 import numpy as np
+from scipy import special
 
 TWO_PI = 2.0 * math.pi
 
@@ -327,13 +328,32 @@ def ddi_apply_adjoint(sigma: np.ndarray, prob: DDIProblem) -> np.ndarray:
 
 
 # --------------------------------------------------------------------------
-# The split of Eq. 3.9 (3D): Phi ~ I_1 + I_2 with a partition of unity in k
+# The split of Eq. 3.9: Phi ~ I_1 + I_2 with a partition of unity in k
 # --------------------------------------------------------------------------
 def split_q(k: np.ndarray, s: float) -> np.ndarray:
-    """q(k) = exp(-|k|^2 / s^2): smooth, exponentially decaying, and (1 - q) Uhat is smooth in
-    3D because (1 - q)/|k|^2 is an entire function of |k|^2 (the choice of q is a reading; the
-    paper only asks for these properties)."""
-    return np.exp(-np.sum(np.asarray(k) ** 2, axis=-1) / (s * s))
+    """The partition q of Eq. 3.9 at nodes k of shape (M, d) (a reading; the paper asks for a C^inf q
+    that decays exponentially with p = (1 - q) Uhat smooth):
+
+    3D: q = exp(-|k|^2 / s^2).  Uhat is homogeneous of degree 0, P(k)/|k|^2 with P quadratic, and
+        (1 - q)/|k|^2 is an entire function of |k|^2, so p is smooth (entire).
+    2D: q = erfc(|k| / s).  The 2D symbol is homogeneous of degree 1, P(k)/|k|, so p is smooth only
+        if (1 - q)/|k| is; a q that is smooth in |k|^2 leaves an odd power of |k| in p.  With
+        1 - q = erf(|k|/s), erf(z)/z is an even entire function and p is entire.  q is C^inf as a
+        function of |k| (all the polar rule of I_2 integrates) and decays like exp(-|k|^2/s^2).
+
+    In both dimensions the kernel of I_1 then decays like exp(-s^2 r^2 / 4)."""
+    k = np.asarray(k)
+    kk = np.sum(k * k, axis=-1)
+    if k.shape[-1] == 3:
+        return np.exp(-kk / (s * s))
+    return special.erfc(np.sqrt(kk) / s)
+
+
+def split_one_minus_q(u: np.ndarray, s: float, dim: int) -> np.ndarray:
+    """1 - q at |k|^2 = u, evaluated without cancellation: -expm1(-u/s^2) (3D), erf(|k|/s) (2D)."""
+    if dim == 3:
+        return -np.expm1(-u / (s * s))
+    return special.erf(np.sqrt(u) / s)
 
 
 def split_defaults(L, tol: float):
@@ -350,42 +370,44 @@ def split_defaults(L, tol: float):
 
 
 def split_short_range(rho: np.ndarray, prob: DDIProblem, s: float) -> np.ndarray:
-    """I_1 of Eq. 3.9: (2 pi)^-3 int_Omega exp(i k.x) p(k) rhohat(k) dk, p = (1 - q) Uhat,
-    over the Nyquist box Omega = {|k_i| <= pi/h_i}, by the regular FFT.
+    """I_1 of Eq. 3.9: (2 pi)^-d int_Omega exp(i k.x) p(k) rhohat(k) dk, p = (1 - q) Uhat,
+    over the Nyquist box Omega = {|k_i| <= pi/h_i}, by the regular FFT (3D and 2D).
 
     The trapezoid rule in k on the grid of the box zero-padded to [-L, 3L) per axis
     (2 N_i points, k_m = 2 pi m / (2 N_i h_i), m in (-N_i, N_i): the Nyquist planes
     m_i = -N_i are left out, so the set is symmetric and the sum real), with rhohat(k_m) the
     trapezoid rule of the transform.  With F = fftn of rho padded with zeros at the end,
-    rhohat(k_m) = prod(h) exp(-i k_m L) F_m and (2 pi)^-3 prod(dk) prod(h) = 1/prod(2N), so
+    rhohat(k_m) = prod(h) exp(-i k_m L) F_m and (2 pi)^-d prod(dk) prod(h) = 1/prod(2N), so
     I_1 = ifftn(p F) on the first N_i points of each axis.  (The FFT is the library step
     that evaluates these trapezoid sums; nothing else is reordered.)
     """
-    if prob.dim != 3:
-        raise ValueError("the split is built for 3D")
+    d = prob.dim
     rho = np.asarray(rho, dtype=np.float64)
     pad = tuple(2 * n for n in prob.n)
-    F = np.fft.fftn(rho, s=pad, axes=(0, 1, 2))
+    F = np.fft.fftn(rho, s=pad, axes=tuple(range(d)))
     ks = [TWO_PI * np.fft.fftfreq(2 * n, d=h) for n, h in zip(prob.n, prob.h)]
     K = np.stack(np.meshgrid(*ks, indexing="ij"), axis=-1)
     u = np.sum(K * K, axis=-1)
     n = np.asarray(prob.dip_n, dtype=np.float64)
     m = n if prob.dip_m is None else np.asarray(prob.dip_m, dtype=np.float64)
     with np.errstate(invalid="ignore", divide="ignore"):
-        U = 3.0 * (K @ n) * (K @ m) / u - float(n @ m)
-    p = -np.expm1(-u / (s * s)) * U
-    p[u == 0.0] = 0.0                                    # (1 - q) vanishes at k = 0
+        if d == 3:
+            U = 3.0 * (K @ n) * (K @ m) / u - float(n @ m)
+        else:
+            U = 3.0 * ((K @ n[:2]) * (K @ m[:2]) - n[2] * m[2] * u) / (2.0 * np.sqrt(u))
+    p = split_one_minus_q(u, s, d) * U
+    p[u == 0.0] = 0.0                                    # (1 - q) Uhat vanishes at k = 0
     for ax, na in enumerate(prob.n):                     # Nyquist planes m_i = -N_i
-        idx = [slice(None)] * 3
+        idx = [slice(None)] * d
         idx[ax] = na
         p[tuple(idx)] = 0.0
     out = np.fft.ifftn(p * F)
-    return out.real[:prob.n[0], :prob.n[1], :prob.n[2]].copy()
+    return out.real[tuple(slice(0, na) for na in prob.n)].copy()
 
 
 def split_long_range_nodes(prob: DDIProblem, s: float):
-    """(k_q, c_q q(k_q)) for I_2 of Eq. 3.9: the spherical quadrature of Eq. DDI-Trun1 on the
-    ball of radius prob.kmax, weights times q."""
+    """(k_q, c_q q(k_q)) for I_2 of Eq. 3.9: the spherical (3D) or polar (2D) quadrature of
+    Eq. DDI-Trun1 on the ball of radius prob.kmax, weights times q."""
     quad = quadrature(prob)
     return quad.k, node_coefficients(prob, quad) * split_q(quad.k, s)
 

@@ -7,6 +7,8 @@ symbol or a transposed axis in the quadrature shows up as an O(1) error here.
 * ``phi_gaussian_3d``: Ex. 2.1, rho = exp(-|x|^2/sigma^2), Phi = -(n.m) rho - 3 n^T G m
   with the Hessian G of Eq. Hessian_Ex1.
 * ``phi_gaussian_2d``: Ex. 2.2, rho = exp(-|x|^2/sigma^2) in 2D, the I0/I1 form.
+* ``phi_gaussian_2d_radial``: the same Phi by its Fourier integral in polar coordinates (J0, J2),
+  optionally with a radial weight: with the partition q of Eq. 3.9 it gives I_2 of the split.
 * ``phi_gaussian_product``: Ex. 2.3.  For rho = prod_i G_{a_i}(x_i - c_i) with the
   heat kernel G_b(y) = (4 pi b)^(-1/2) exp(-y^2/(4b)), the Poisson potential is
   u = int_0^inf prod_i G_{a_i+s} ds (3D, as in Eqs. Coulomb:3D:aniso:z/xy) and the
@@ -184,3 +186,37 @@ def gaussian_lumps_to_products(lumps, scale=1.0):
 def phi_mixture(point, products, dip_n, dip_m=None, epsrel=1e-12):
     """Sum of phi_gaussian_product over the expansion of gaussian_lumps_to_products."""
     return sum(w * phi_gaussian_product(point, a, c, dip_n, dip_m, epsrel) for w, a, c in products)
+
+
+def phi_gaussian_2d_radial(x, y, sigma, dip_n, dip_m=None, weight=None, epsabs=1e-17):
+    """Ex. 2.2 by its Fourier integral in polar coordinates, optionally with a radial weight w(|k|):
+    for rho = exp(-|x|^2/sigma^2), rhohat(k) = pi sigma^2 exp(-sigma^2 |k|^2/4), and with
+    k = |k| (cos t, sin t) the 2D symbol is 3/2 |k| [A0 - n3 m3 + Ac cos 2t + As sin 2t],
+    A0 = (n1 m1 + n2 m2)/2, Ac = (n1 m1 - n2 m2)/2, As = (n1 m2 + n2 m1)/2.  The angular integral
+    of exp(i k.x) against 1, cos 2t, sin 2t gives 2 pi J0(|k| r) and -2 pi J2(|k| r) (cos 2p, sin 2p)
+    at x = r (cos p, sin p), so
+        Phi(x) = 3/(4 pi) int_0^inf k^2 w(k) rhohat(k) [(A0 - n3 m3) J0(kr) - J2(kr)(Ac cos 2p + As sin 2p)] dk.
+    With w = 1 this is Phi of Ex. 2.2 (an independent form of phi_gaussian_2d); with w = q it is
+    I_2 of Eq. 3.9 for that density.  Evaluated point by point with adaptive Gauss-Kronrod.
+    """
+    n = np.asarray(dip_n, float)
+    m = n if dip_m is None else np.asarray(dip_m, float)
+    A0 = 0.5 * (n[0] * m[0] + n[1] * m[1]) - n[2] * m[2]
+    Ac = 0.5 * (n[0] * m[0] - n[1] * m[1])
+    As = 0.5 * (n[0] * m[1] + n[1] * m[0])
+    x, y = np.broadcast_arrays(np.asarray(x, float), np.asarray(y, float))
+    out = np.empty(x.shape)
+    kcut = 2.0 * math.sqrt(math.log(1e300)) / sigma          # rhohat below 1e-300 beyond
+    for idx in np.ndindex(x.shape):
+        r = math.hypot(x[idx], y[idx])
+        ph = math.atan2(y[idx], x[idx])
+        ang = Ac * math.cos(2 * ph) + As * math.sin(2 * ph)
+
+        def f(k):
+            w = 1.0 if weight is None else weight(k)
+            rh = math.pi * sigma * sigma * math.exp(-sigma * sigma * k * k / 4)
+            return k * k * w * rh * (A0 * special.j0(k * r) - special.jv(2, k * r) * ang)
+
+        val, _ = integrate.quad(f, 0.0, kcut, epsabs=epsabs, epsrel=1e-13, limit=500)
+        out[idx] = 3.0 / (4.0 * math.pi) * val
+    return out

@@ -373,6 +373,59 @@ def test_gradient_flow_fixed_point_is_discrete_ground_state():
     assert np.max(np.abs(cur - phi_g)) < 0.05 * d0
 
 
+def test_chemical_potential_is_the_rayleigh_quotient():
+    """mu = E + E_int + E_dip (Sec. 3.2) equals <psi, H psi> for any normalised psi, computed here
+    from the gradient G = prod(h) H psi (a different code path: sum conj(psi) G); at the discrete
+    harmonic ground state (beta = lam = 0) it is the eigenvalue of the dense eigensolve."""
+    n, L = (12, 12, 12), (6.0,) * 3
+    lumps, _ = I.mixture_lumps(4, 3, (2, 3), centre=1.0, widths=(0.8, 1.5))
+    psi, _ = I.normalise(I.lumps_on_grid(lumps, n, L), n, L)
+    p = O.DDIProblem(dim=3, n=n, L=L, dip_n=(0.6, 0.0, 0.8), n_rad=12, n_pol=6, n_azi=12)
+    gp = O.GPEParams(beta=30.0, lam=-20.0, gamma=(1.0, 1.5, 2.0))
+    E, G = O.gpe_energy_grad(psi, p, gp)
+    rq = float(np.real(np.vdot(psi, G)))
+    assert abs(O.chemical_potential(E) - rq) < 1e-12 * abs(rq)
+    n2 = (16, 16, 16)
+    phi_g, e_g = _discrete_harmonic_ground_state(n2, L, (1.0, 1.5, 2.0))
+    p2 = O.DDIProblem(dim=3, n=n2, L=L, n_rad=4, n_pol=2, n_azi=4)
+    E2, _ = O.gpe_energy_grad(phi_g, p2, O.GPEParams(gamma=(1.0, 1.5, 2.0)), grad=False)
+    assert abs(O.chemical_potential(E2) - e_g) < 1e-12
+
+
+def test_virial_is_the_dilation_derivative_of_the_energy():
+    """I = 2 E_kin - 2 E_pot + 3 E_int + 3 E_dip (Eq. vir_iden) is dE/da at a = 1 of the dilation
+    psi_a(x) = a^(3/2) psi(a x), which keeps the mass: the kinetic part scales as a^2, the trap as
+    a^-2, the contact and dipolar parts as a^3 (U_dip is homogeneous of degree -3).  Checked by a
+    central difference of the oracle's energy of the dilated state on the grid (beta, lam != 0);
+    at a ground state the derivative, hence I, vanishes."""
+    n, L = (32, 32, 32), (8.0,) * 3
+    gp = O.GPEParams(beta=40.0, lam=25.0, gamma=(1.0, 1.3, 1.6))
+    p = O.DDIProblem(dim=3, n=n, L=L, dip_n=(0.6, 0.0, 0.8), n_rad=48, n_pol=24, n_azi=48)
+    lumps, _ = I.mixture_lumps(3, 3, (2, 2), centre=0.7, widths=(1.0, 1.4))
+    cell = p.cell
+
+    def energy(a):
+        # psi_a on the grid from the analytic lumps: a^(3/2) psi(a x), exactly normalised by the
+        # same factor as psi (the grid sum of a smooth decaying function is its integral)
+        psi_a = a ** 1.5 * I.lumps_on_grid([(c, np.asarray(m) / a, np.asarray(w) / a) for c, m, w in lumps], n, L)
+        return O.gpe_energy_grad(psi_a / norm, p, gp, grad=False)[0]
+
+    psi1 = I.lumps_on_grid(lumps, n, L)
+    norm = math.sqrt(cell * float(np.sum(np.abs(psi1) ** 2)))
+    E = energy(1.0)
+    d = 1e-4
+    dEda = (energy(1.0 + d)[4] - energy(1.0 - d)[4]) / (2 * d)
+    assert abs(O.virial(E) - dEda) < 1e-6 * np.max(np.abs(E[:4]))
+    assert abs(O.virial(E)) > 0.1                       # not at a ground state: a non-trivial check
+    # the discrete harmonic ground state (beta = lam = 0) on a resolving grid: I vanishes
+    # (E_kin = E_pot), to the grid's spectral accuracy
+    n2 = (32, 32, 32)
+    phi_g, _ = _discrete_harmonic_ground_state(n2, (6.0,) * 3, (1.0, 1.5, 2.0))
+    p2 = O.DDIProblem(dim=3, n=n2, L=(6.0,) * 3, n_rad=4, n_pol=2, n_azi=4)
+    E2, _ = O.gpe_energy_grad(phi_g, p2, O.GPEParams(gamma=(1.0, 1.5, 2.0)), grad=False)
+    assert abs(O.virial(E2)) < 1e-10 * E2[4]
+
+
 def test_gradient_flow_energy_decreases_with_dipoles():
     n, L = (16, 16, 16), (6.0,) * 3
     gp = O.GPEParams(beta=20.0, lam=15.0, gamma=(1.0, 1.0, 2.0))
@@ -697,3 +750,98 @@ def test_time_splitting_case_iii_matches_ode_integration(q, delta):
     # delta -> 0: Case I
     assert np.max(np.abs(O.ts_step(psi, p, gp, dt=dt, delta=1e-9, q=q) - O.ts_step(psi, p, gp, dt=dt))) \
         < 1e-8 * np.max(np.abs(psi))
+
+
+# ---------------------------------------------------------------- the split of Eq. 3.9 in 2D
+_T3 = {"n": (0, -0.896, 0.44404), "m": (0, -0.52476, 0.85125)}      # the axes of Ex. 2.2 / Table 3
+_SIG2 = math.sqrt(1.3)
+
+
+def test_refs_2d_polar_integral_equals_bessel_form():
+    """The polar Fourier integral (J0, J2) and the I0/I1 closed form of Ex. 2.2 are independent
+    forms of the same Phi."""
+    for nv, mv, sig in ((_T3["n"], _T3["m"], _SIG2), ((0.6, 0.0, 0.8), (0.3, 0.4, 0.866), 1.0)):
+        for pt in [(0.3, 0.2), (1.0, 2.0), (0.0, 0.0), (-2.5, 0.7), (10.0, -7.0)]:
+            a = R.phi_gaussian_2d(*pt, sig, nv, mv)
+            b = float(R.phi_gaussian_2d_radial(pt[0], pt[1], sig, nv, mv))
+            assert abs(a - b) < 1e-14 * max(1.0, abs(a))
+
+
+def _split2d_case(L, N):
+    prob = O.DDIProblem(dim=2, n=(N, N), L=(L, L), dip_n=_T3["n"], dip_m=_T3["m"], n_rad=32, n_azi=64)
+    s, R2 = O.split_defaults(prob.L, 1e-13)
+    prob.kmax = R2
+    rho = I.gaussian_density((N, N), (L, L), _SIG2)
+    rng = np.random.default_rng(8)
+    pts = np.concatenate([rng.integers(0, N, size=(10, 2)), np.array([[0, 0], [N // 2, N // 2], [N // 2, 0],
+                                                                        [N - 1, N // 3]])])
+    xs = prob.axes()
+    X = np.array([[xs[0][p[0]], xs[1][p[1]]] for p in pts])
+    return prob, s, rho, pts, X
+
+
+def _i2_exact(X, s):
+    return R.phi_gaussian_2d_radial(X[:, 0], X[:, 1], _SIG2, _T3["n"], _T3["m"],
+                                    weight=lambda k: math.erfc(k / s))
+
+
+def test_split_2d_short_range_is_exact_ddi_minus_long_range():
+    """I_1 (padded FFT with p = erf(|k|/s) Uhat) at sampled points equals the exact DDI of Ex. 2.2
+    minus the exact I_2 (the polar integral with weight q = erfc(|k|/s)), to round-off."""
+    prob, s, rho, pts, X = _split2d_case(16.0, 128)
+    i1 = O.split_short_range(rho, prob, s)
+    ex = R.phi_gaussian_2d(X[:, 0], X[:, 1], _SIG2, _T3["n"], _T3["m"])
+    ex1 = ex - _i2_exact(X, s)
+    got = np.array([i1[tuple(p)] for p in pts])
+    assert np.max(np.abs(got - ex1)) < 1e-13 * np.max(np.abs(ex))
+    assert np.max(np.abs(ex1)) > 0.1 * np.max(np.abs(ex))          # a real share of Phi
+
+
+def test_split_2d_long_range_nodes_with_exact_transform():
+    """The I_2 nodes (polar rule on the ball of radius R_2, weights times erfc(|k|/s)) with the exact
+    rhohat reproduce the exact I_2 (pins q, R_2 and the 2D weights of the small ball)."""
+    prob, s, _, pts, X = _split2d_case(16.0, 128)
+    k, c = O.split_long_range_nodes(prob, s)
+    assert k.shape[0] == 32 * 64                                   # the small ball lies inside the box
+    rh = math.pi * 1.3 * np.exp(-1.3 * np.sum(k * k, axis=1) / 4)
+    got = O.nodes_to_points(c * rh, prob, k, pts)
+    ex2 = _i2_exact(X, s)
+    ex = R.phi_gaussian_2d(X[:, 0], X[:, 1], _SIG2, _T3["n"], _T3["m"])
+    assert np.max(np.abs(got - ex2)) < 1e-13 * np.max(np.abs(ex))
+
+
+def test_split_2d_long_range_equals_full_rule_restricted_to_the_ball():
+    """I_2 on the small ball equals the full ball's rule with its weights times q (q < 1e-13
+    beyond R_2), from the grid's own transform."""
+    prob, s, rho, pts, _ = _split2d_case(8.0, 64)
+    i2 = O.split_long_range(rho, prob, s)
+    full = O.DDIProblem(dim=2, n=prob.n, L=prob.L, dip_n=_T3["n"], dip_m=_T3["m"], n_rad=256, n_azi=256)
+    kf, cf = O.split_long_range_nodes(full, s)
+    i2f = O.nodes_to_grid(cf * O.rhohat(rho, full, kf), full, kf)
+    assert np.max(np.abs(i2 - i2f)) < 1e-13 * np.max(np.abs(i2f))
+
+
+@pytest.mark.parametrize("cell", [c for c in _tables()["table3_2d"]["cells"] if c["h"] == 0.25 and c["L"] >= 8],
+                         ids=lambda c: f"L{c['L']}")
+def test_split_2d_apply_reproduces_table3(cell):
+    """I_1 + I_2 from the grid against Ex. 2.2 at the Table 3 cells L = 8, 16 (h = 1/4): e_h at the
+    paper's NUFFT level (4.720e-14, 3.489e-14) with 32 x 64 nodes on the small ball instead of the
+    full ball's 128 x 256."""
+    L = float(cell["L"])
+    N = int(round(2 * L / 0.25))
+    prob, s, rho, _, _ = _split2d_case(L, N)
+    phi = O.split_apply(rho, prob, s)
+    x, y = np.meshgrid(*I.grid_axes((N, N), (L, L)), indexing="ij")
+    e = O.rel_l2(phi, R.phi_gaussian_2d(x, y, _SIG2, _T3["n"], _T3["m"]))
+    assert e < 3 * cell["e_h"], (e, cell["e_h"])
+
+
+def test_split_2d_short_range_symmetric():
+    """The 2D padded convolution with an even real multiplier over a symmetric set is symmetric."""
+    prob = O.DDIProblem(dim=2, n=(32, 32), L=(5.0, 5.0), dip_n=(0.48, -0.6, 0.64))
+    rng = np.random.default_rng(3)
+    r1 = rng.standard_normal(prob.n)
+    r2 = rng.standard_normal(prob.n)
+    a = np.sum(r2 * O.split_short_range(r1, prob, 0.9))
+    b = np.sum(r1 * O.split_short_range(r2, prob, 0.9))
+    assert abs(a - b) < 1e-12 * np.sum(np.abs(r2 * O.split_short_range(r1, prob, 0.9)))
