@@ -81,10 +81,12 @@ typedef enum { DDI_FP64 = 0, DDI_MIXED = 1 } ddi_precision;
  *  prec         DDI_FP64 or DDI_MIXED (FP32 grids, spread, interp and FFT).
  *  kernel_width 0 = from tol; else the width w (4..16) of the
  *               exponential-of-semicircle kernel.
- *  split        0: the quadrature over the whole ball (above).  1 (3D only;
- *               2D returns DDI_ENOTSUP): the split of Sec. 2.1, Eq. 3.9,
- *               Phi = I_1 + I_2 with the partition q(k) = exp(-|k|^2/s^2):
- *                 I_1 = (2 pi)^-3 int over the Nyquist box |k_i| < pi/h_i of
+ *  split        0: the quadrature over the whole ball (above).  1: the split of
+ *               Sec. 2.1, Eq. 3.9, Phi = I_1 + I_2 with the partition
+ *               q(k) = exp(-|k|^2/s^2) in 3D and q(k) = erfc(|k|/s) in 2D (where
+ *               the symbol grows like |k|: with 1 - q = erf(|k|/s), (1 - q) Uhat
+ *               is smooth):
+ *                 I_1 = (2 pi)^-d int over the Nyquist box |k_i| < pi/h_i of
  *                       exp(i k.x) (1 - q(k)) Uhat(k) rhohat(k) dk, by the
  *                       trapezoid rule of the box zero-padded to 2 n_i points
  *                       per axis (k_m = pi m / (2 L_i), |m| < n_i; the Nyquist
@@ -213,10 +215,12 @@ ddi_status gpe_energy_grad(ddi_plan_t plan, const gpe_params* gp, const void* ps
  * B = V + beta |psi_in|^2 + lambda Phi^n, alpha = (max B + min B)/2:
  *   (1/dt + alpha - 1/2 Lap) phi1_{j+1} = psi_in/dt + (alpha - B) phi1_j,  phi1_0 = psi_in,
  * then psi_out = phi1 / sqrt(prod(h) sum |phi1|^2).  psi_in, psi_out: complex
- * grids (may be the same buffer).  Does not synchronise.
+ * grids (may be the same buffer).  residual_dev (nullable): one device double that receives
+ * the stopping quantity of Sec. 3.1, max_l |psi_out_l - psi_in_l| / dt, computed from the stored
+ * values.  Does not synchronise.
  */
 ddi_status gpe_gf_step(ddi_plan_t plan, const gpe_params* gp, double dt, int32_t n_inner,
-                       const void* psi_in_dev, void* psi_out_dev, void* stream);
+                       const void* psi_in_dev, void* psi_out_dev, double* residual_dev, void* stream);
 
 /*
  * One step of the second-order time splitting for the dipolar GPE dynamics (Sec. 4.1,

@@ -8,6 +8,7 @@
 #include <new>
 #include <string>
 
+#include "alloc_group.h"
 #include "ddi_internal.h"
 
 struct ddi_plan_s {
@@ -50,7 +51,7 @@ void free_plan(ddi::DevicePlan& P) {
   if (P.aux) (void)hipStreamDestroy(P.aux);
   void* ptrs[] = {P.nodes, P.c_scaled, P.c_half, P.ones, P.fine_short, P.kq, P.base_scaled, P.base_half,
                   P.deconv[0], P.deconv[1], P.deconv[2],
-                  P.fine, P.gnodes, P.partial, P.ipartial, P.pads, P.gpe_rho, P.gpe_phi, P.gpe_phit, P.gpe_c1, P.gpe_c2, P.gpe_red};
+                  P.fine, P.gnodes, P.partial, P.ipartial, P.pads, P.gpe.rho, P.gpe.phi, P.gpe.phit, P.gpe.c1, P.gpe.c2, P.gpe.red};
   for (auto& d : P.dsched) {
     void* sp[] = {d.list, d.items, d.reduces, d.interp_items, d.interp_direct, d.gptr, d.gpos, d.ent};
     for (void* p : sp)
@@ -163,19 +164,22 @@ ddi_status build_device(ddi::DevicePlan& P, hipStream_t s, std::vector<ddi::Node
   return DDI_OK;
 }
 
+// The GPE workspace (allocated on the first GPE call): all of it or none, so that a call after a
+// failed allocation allocates again instead of running on missing buffers.
 template <typename T>
 ddi_status ensure_gpe(ddi::DevicePlan& P) {
-  if (P.gpe_rho) return DDI_OK;
+  if (P.gpe.rho) return DDI_OK;
   const int64_t n = static_cast<int64_t>(P.H.N[0]) * P.H.N[1] * P.H.N[2];
-  P.gpe_red_blocks = ddi::gpe_reduction_blocks<T>(P);
-  HIP_TRY(hipMalloc(&P.gpe_rho, n * sizeof(T)), "allocate GPE workspace");
-  HIP_TRY(hipMalloc(&P.gpe_phi, n * sizeof(T)), "allocate GPE workspace");
-  HIP_TRY(hipMalloc(&P.gpe_phit, n * sizeof(T)), "allocate GPE workspace");
-  HIP_TRY(hipMalloc(&P.gpe_c1, n * sizeof(ddi::Complex<T>)), "allocate GPE workspace");
-  HIP_TRY(hipMalloc(&P.gpe_c2, n * sizeof(ddi::Complex<T>)), "allocate GPE workspace");
-  HIP_TRY(hipMalloc(reinterpret_cast<void**>(&P.gpe_red), (8 * P.gpe_red_blocks + 16) * sizeof(double)),
-          "allocate GPE workspace");
-  P.workspace_bytes += n * (3 * sizeof(T) + 2 * sizeof(ddi::Complex<T>));
+  const int nb = ddi::gpe_reduction_blocks<T>(P);
+  ddi::GpeWork& W = P.gpe;
+  void** ptrs[] = {&W.rho, &W.phi, &W.phit, &W.c1, &W.c2, reinterpret_cast<void**>(&W.red)};
+  const size_t bytes[] = {n * sizeof(T), n * sizeof(T), n * sizeof(T), n * sizeof(ddi::Complex<T>),
+                          n * sizeof(ddi::Complex<T>), ddi::gpe_red_doubles(nb) * sizeof(double)};
+  const int e = ddi::alloc_group(
+      ptrs, bytes, 6, [](void** p, size_t b) { return hipMalloc(p, b); }, [](void* p) { (void)hipFree(p); });
+  if (e != 0) return hip_fail(static_cast<hipError_t>(e), "allocate GPE workspace");
+  W.red_blocks = nb;
+  for (size_t b : bytes) P.workspace_bytes += static_cast<int64_t>(b);
   return DDI_OK;
 }
 
@@ -481,10 +485,10 @@ ddi_status gpe_energy_grad(ddi_plan_t plan, const gpe_params* gp, const void* ps
   st = P.mixed ? ensure_gpe<float>(P) : ensure_gpe<double>(P);
   if (st != DDI_OK) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  double* E_dev = P.gpe_red + 8 * P.gpe_red_blocks + 8;
-  hipError_t e = P.mixed ? ddi::run_gpe_energy_grad<float>(P, *gp, static_cast<const ddi::Complex<float>*>(psi_dev), E_dev,
+  double* E_dev = P.gpe.red + 8 * P.gpe.red_blocks + 8;
+  hipError_t e = P.mixed ? ddi::run_gpe_energy_grad<float>(P, P.gpe, *gp, static_cast<const ddi::Complex<float>*>(psi_dev), E_dev,
                                                            static_cast<ddi::Complex<float>*>(grad_dev), s)
-                         : ddi::run_gpe_energy_grad<double>(P, *gp, static_cast<const ddi::Complex<double>*>(psi_dev), E_dev,
+                         : ddi::run_gpe_energy_grad<double>(P, P.gpe, *gp, static_cast<const ddi::Complex<double>*>(psi_dev), E_dev,
                                                             static_cast<ddi::Complex<double>*>(grad_dev), s);
   if (e != hipSuccess) return hip_fail(e, "gpe_energy_grad launch");
   HIP_TRY(hipMemcpyAsync(E_out, E_dev, 5 * sizeof(double), hipMemcpyDeviceToHost, s), "copy energies");
@@ -493,7 +497,7 @@ ddi_status gpe_energy_grad(ddi_plan_t plan, const gpe_params* gp, const void* ps
 }
 
 ddi_status gpe_gf_step(ddi_plan_t plan, const gpe_params* gp, double dt, int32_t n_inner, const void* psi_in_dev,
-                       void* psi_out_dev, void* stream) {
+                       void* psi_out_dev, double* residual_dev, void* stream) {
   ddi_status st = check_plan(plan);
   if (st != DDI_OK) return st;
   if (!gp || !psi_in_dev || !psi_out_dev) return fail(DDI_EINVAL, "NULL argument");
@@ -504,9 +508,9 @@ ddi_status gpe_gf_step(ddi_plan_t plan, const gpe_params* gp, double dt, int32_t
   if (st != DDI_OK) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   hipError_t e = P.mixed ? ddi::run_gf_step<float>(P, *gp, dt, n_inner, static_cast<const ddi::Complex<float>*>(psi_in_dev),
-                                                   static_cast<ddi::Complex<float>*>(psi_out_dev), s)
+                                                   static_cast<ddi::Complex<float>*>(psi_out_dev), residual_dev, s)
                          : ddi::run_gf_step<double>(P, *gp, dt, n_inner, static_cast<const ddi::Complex<double>*>(psi_in_dev),
-                                                    static_cast<ddi::Complex<double>*>(psi_out_dev), s);
+                                                    static_cast<ddi::Complex<double>*>(psi_out_dev), residual_dev, s);
   if (e != hipSuccess) return hip_fail(e, "gpe_gf_step launch");
   return DDI_OK;
 }

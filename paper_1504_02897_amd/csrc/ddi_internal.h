@@ -214,6 +214,20 @@ __device__ inline int xcd_remap(int b, int nb) {
     if (e_ != hipSuccess) return e_; \
   } while (0)
 
+// Workspace of the GPE kernels on an N0 x N1 x N2 grid of the plan's real type T.
+struct GpeWork {
+  void* rho = nullptr;           // T[N]
+  void* phi = nullptr;           // T[N]
+  void* phit = nullptr;          // T[N]
+  void* c1 = nullptr;            // Complex<T>[N]
+  void* c2 = nullptr;            // Complex<T>[N] (gradient flow only)
+  double* red = nullptr;         // reduction scratch: gpe_red_doubles(red_blocks) doubles
+  int red_blocks = 0;
+};
+// Doubles of the reduction scratch: 4 slots per block for two reductions, then 8 scalars (the
+// gradient flow's alpha), then the 5 energies (at offset 8 nb + 8).
+inline size_t gpe_red_doubles(int nb) { return 8 * static_cast<size_t>(nb) + 16; }
+
 // Device-resident plan state.
 struct DevicePlan {
   HostTables H;
@@ -256,13 +270,7 @@ struct DevicePlan {
                                  // FP64), then a zero record that positions outside a window read
   int64_t workspace_bytes = 0;
   // GPE workspace (allocated on first use)
-  void* gpe_rho = nullptr;       // T[N]
-  void* gpe_phi = nullptr;       // T[N]
-  void* gpe_phit = nullptr;      // T[N]
-  void* gpe_c1 = nullptr;        // Complex<T>[N]
-  void* gpe_c2 = nullptr;        // Complex<T>[N]
-  double* gpe_red = nullptr;     // reduction scratch
-  int gpe_red_blocks = 0;
+  GpeWork gpe;
 };
 
 // Kernel launchers (kernels.hip), templated on the real type.
@@ -287,11 +295,11 @@ template <typename T>
 hipError_t run_ddi(DevicePlan& P, const T* rho, T* phi, int sign, hipStream_t s, hipEvent_t* ev);
 constexpr int kStages = 9;
 template <typename T>
-hipError_t run_gpe_energy_grad(DevicePlan& P, const gpe_params& gp, const Complex<T>* psi, double* E_dev,
-                               Complex<T>* grad, hipStream_t s);
+hipError_t run_gpe_energy_grad(DevicePlan& P, const GpeWork& W, const gpe_params& gp, const Complex<T>* psi,
+                               double* E_dev, Complex<T>* grad, hipStream_t s);
 template <typename T>
 hipError_t run_gf_step(DevicePlan& P, const gpe_params& gp, double dt, int n_inner, const Complex<T>* psi_in,
-                       Complex<T>* psi_out, hipStream_t s);
+                       Complex<T>* psi_out, double* residual, hipStream_t s);
 template <typename T>
 hipError_t run_ts_step(DevicePlan& P, const gpe_params& gp, double dt, double delta, double q,
                        const Complex<T>* psi_in, Complex<T>* psi_out, hipStream_t s);

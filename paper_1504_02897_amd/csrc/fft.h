@@ -11,14 +11,20 @@ namespace ddi {
 // and writes the real part to a compact grid.
 enum ContigMode { R2C_PAD = 0, C2C = 1, C2R_TRUNC = 2, C2R_ADD = 3 };   // C2R_ADD: as C2R_TRUNC, added to the output
 
-// The multiplier of the split's short-range part (Eq. 3.9) on the zero-padded grid:
-// (1 - exp(-|k|^2/s^2)) (3 (n.k)(m.k)/|k|^2 - n.m) at k_i = m_i dk[i], times scale.
+// The multiplier of the split's short-range part (Eq. 3.9) on the zero-padded grid, p = (1 - q) Uhat
+// at k_i = m_i dk[i], times scale:
+//   3D: (1 - exp(-|k|^2/s^2)) (3 (n.k)(m.k)/|k|^2 - n.m);
+//   2D: erf(|k|/s) 3 [(n.k)(m.k) - n3 m3 |k|^2] / (2 |k|), the paper's (x, y) carried on the
+//       kernel's axes 0 and 2 (n = (n1, 0, n2), dk[1] unused).
 struct SplitSymbol {
   double n[3], m[3];
   double nm;
   double inv_s2;
   double dk[3];
   double scale;
+  int dim;            // 3, or 2 for the quasi-2D symbol
+  double inv_s;       // 1/s (2D)
+  double n3m3;        // n3 m3 (2D)
 };
 
 // In-place transforms of length n along axis 0 or 1 of a [d0][d1][d2] complex
@@ -47,6 +53,7 @@ hipError_t launch_contig(int n, const void* in, void* out, int n0, int n1, int d
 // with exp(-2 pi i jk/n), multiply by the split symbol times 1 at m2 = 0 and 2 above (the
 // half set; the partner modes are the complex conjugates), zero on the Nyquist planes
 // m_i = -d_i/2, transform back with exp(+2 pi i jk/n) and write the nc active outputs.
+// A 2D spectrum [n][d2] is passed as d1 = 1 (its lines along axis 0 are then the paper's x).
 template <typename T>
 hipError_t launch_symbol(int n, Complex<T>* F, int d1, int d2, int nc, int nz, const SplitSymbol& sp,
                          const Complex<T>* tw, hipStream_t s);

@@ -320,7 +320,12 @@ __global__ void __launch_bounds__(MAXT, 1024 / MAXT) k_fft_symbol(C<T>* __restri
     if (!nyq1 && 2 * k != N && u > 0.0) {
       const double kn = k0 * sp.n[0] + kn12;
       const double km = k0 * sp.m[0] + km12;
-      mult[i] = -expm1(-u * sp.inv_s2) * (3.0 * kn * km / u - sp.nm) * w2;
+      if (sp.dim == 3) {
+        mult[i] = -expm1(-u * sp.inv_s2) * (3.0 * kn * km / u - sp.nm) * w2;
+      } else {
+        const double kk = sqrt(u);
+        mult[i] = erf(kk * sp.inv_s) * (1.5 * (kn * km - sp.n3m3 * u) / kk) * w2;
+      }
     }
   }
   C<T> v[P::R1];

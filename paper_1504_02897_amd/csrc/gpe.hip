@@ -242,16 +242,42 @@ __global__ void __launch_bounds__(kRedThreads) k_norm2(const C<T>* __restrict__ 
   block_sum4(v, red);
 }
 
-// y <- x / sqrt(cell * sum) (y may be x)
-template <typename T>
-__global__ void __launch_bounds__(256) k_normalise(const C<T>* x, C<T>* y, int64_t n, const double* __restrict__ red,
-                                                   int nblocks, double cell) {
+// y <- x / sqrt(cell * sum) (y may be x).  RES: also the block maxima of |y - prev| (the step's
+// change, prev = the step's input, which y may overwrite: each element is read before it is
+// written) to res[block * 4]; launched with one block per reduction slot.
+template <typename T, bool RES>
+__global__ void __launch_bounds__(kRedThreads) k_normalise(const C<T>* x, C<T>* y, const C<T>* prev, int64_t n,
+                                                           const double* __restrict__ red, int nblocks, double cell,
+                                                           double* __restrict__ res) {
   const double f = 1.0 / sqrt(cell * reduce_partials(red, nblocks, 0, 0.0, OpSum()));
+  double mx = 0.0;
   for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
     const C<T> p = x[i];
-    y[i] = C<T>{static_cast<T>(f * p.re), static_cast<T>(f * p.im)};
+    const C<T> v = C<T>{static_cast<T>(f * p.re), static_cast<T>(f * p.im)};
+    if (RES) {
+      const C<T> o = prev[i];
+      mx = fmax(mx, hypot(static_cast<double>(v.re) - o.re, static_cast<double>(v.im) - o.im));
+    }
+    y[i] = v;
   }
+  if (RES) {
+    __shared__ double sm[kRedThreads / 64];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int w = 1; w < kRedThreads / 64; ++w) mx = fmax(mx, sm[w]);
+      res[blockIdx.x * 4] = mx;
+    }
+  }
+}
+
+// out[0] = max over the block maxima / dt: the stopping residual max |phi^{n+1} - phi^n| / dt
+__global__ void k_gf_change(const double* __restrict__ res, int nblocks, double inv_dt, double* __restrict__ out) {
+  const double mx = reduce_partials(res, nblocks, 0, 0.0, OpMax());
+  if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = mx * inv_dt;
 }
 
 // Time splitting (Eq. tssp2): x <- x exp(-i dt |mu|^2 / 4) / prod(N), in Fourier space (the
@@ -355,20 +381,20 @@ static int ew_blocks(int64_t n) {
 }
 
 template <typename T>
-hipError_t run_gpe_energy_grad(DevicePlan& P, const gpe_params& gp, const Complex<T>* psi, double* E_dev,
-                               Complex<T>* grad, hipStream_t s) {
+hipError_t run_gpe_energy_grad(DevicePlan& P, const GpeWork& W, const gpe_params& gp, const Complex<T>* psi,
+                               double* E_dev, Complex<T>* grad, hipStream_t s) {
   const HostTables& H = P.H;
   const int64_t n = static_cast<int64_t>(H.N[0]) * H.N[1] * H.N[2];
   const GridGeo G = geo_of(H, gp);
   const double inv_ntot = 1.0 / static_cast<double>(n);
-  const int nb = P.gpe_red_blocks;
-  T* rho = reinterpret_cast<T*>(P.gpe_rho);
-  T* phi = reinterpret_cast<T*>(P.gpe_phi);
-  T* phit = reinterpret_cast<T*>(P.gpe_phit);
-  C<T>* c1 = reinterpret_cast<C<T>*>(P.gpe_c1);
+  const int nb = W.red_blocks;
+  T* rho = reinterpret_cast<T*>(W.rho);
+  T* phi = reinterpret_cast<T*>(W.phi);
+  T* phit = reinterpret_cast<T*>(W.phit);
+  C<T>* c1 = reinterpret_cast<C<T>*>(W.c1);
   const T* Vext = reinterpret_cast<const T*>(gp.V_dev);
-  double* red_kin = P.gpe_red;
-  double* red_terms = P.gpe_red + 4 * nb;
+  double* red_kin = W.red;
+  double* red_terms = W.red + 4 * nb;
   hipLaunchKernelGGL((k_density<T>), dim3(ew_blocks(n)), dim3(256), 0, s, psi, rho, n);
   DDI_CHECK(hipGetLastError());
   DDI_CHECK(run_ddi<T>(P, rho, phi, +1, s, nullptr));
@@ -392,20 +418,20 @@ hipError_t run_gpe_energy_grad(DevicePlan& P, const gpe_params& gp, const Comple
 
 template <typename T>
 hipError_t run_gf_step(DevicePlan& P, const gpe_params& gp, double dt, int n_inner, const Complex<T>* psi_in,
-                       Complex<T>* psi_out, hipStream_t s) {
+                       Complex<T>* psi_out, double* residual, hipStream_t s) {
   const HostTables& H = P.H;
   const int64_t n = static_cast<int64_t>(H.N[0]) * H.N[1] * H.N[2];
   const GridGeo G = geo_of(H, gp);
   const double inv_ntot = 1.0 / static_cast<double>(n);
-  const int nb = P.gpe_red_blocks;
-  T* rho = reinterpret_cast<T*>(P.gpe_rho);
-  T* phi = reinterpret_cast<T*>(P.gpe_phi);
-  T* Bc = reinterpret_cast<T*>(P.gpe_phit);
-  C<T>* rhs0 = reinterpret_cast<C<T>*>(P.gpe_c1);
-  C<T>* r = reinterpret_cast<C<T>*>(P.gpe_c2);
+  const int nb = P.gpe.red_blocks;
+  T* rho = reinterpret_cast<T*>(P.gpe.rho);
+  T* phi = reinterpret_cast<T*>(P.gpe.phi);
+  T* Bc = reinterpret_cast<T*>(P.gpe.phit);
+  C<T>* rhs0 = reinterpret_cast<C<T>*>(P.gpe.c1);
+  C<T>* r = reinterpret_cast<C<T>*>(P.gpe.c2);
   const T* Vext = reinterpret_cast<const T*>(gp.V_dev);
-  double* red = P.gpe_red;
-  double* scal = P.gpe_red + 8 * nb;
+  double* red = P.gpe.red;
+  double* scal = P.gpe.red + 8 * nb;
   hipLaunchKernelGGL((k_density<T>), dim3(ew_blocks(n)), dim3(256), 0, s, psi_in, rho, n);
   DDI_CHECK(hipGetLastError());
   DDI_CHECK(run_ddi<T>(P, rho, phi, +1, s, nullptr));
@@ -429,7 +455,16 @@ hipError_t run_gf_step(DevicePlan& P, const gpe_params& gp, double dt, int n_inn
   }
   hipLaunchKernelGGL((k_norm2<T>), dim3(nb), dim3(kRedThreads), 0, s, cur, n, red);
   DDI_CHECK(hipGetLastError());
-  hipLaunchKernelGGL((k_normalise<T>), dim3(ew_blocks(n)), dim3(256), 0, s, cur, psi_out, n, red, nb, H.cell);
+  if (residual) {
+    // the block maxima of the change go to the second half of the reduction scratch
+    hipLaunchKernelGGL((k_normalise<T, true>), dim3(nb), dim3(kRedThreads), 0, s, cur, psi_out, psi_in, n, red, nb,
+                       H.cell, red + 4 * nb);
+    DDI_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(k_gf_change, dim3(1), dim3(kRedThreads), 0, s, red + 4 * nb, nb, 1.0 / dt, residual);
+  } else {
+    hipLaunchKernelGGL((k_normalise<T, false>), dim3(nb), dim3(kRedThreads), 0, s, cur, psi_out, psi_in, n, red, nb,
+                       H.cell, nullptr);
+  }
   return hipGetLastError();
 }
 
@@ -445,8 +480,8 @@ hipError_t run_ts_step(DevicePlan& P, const gpe_params& gp, double dt, double de
   const int64_t n = static_cast<int64_t>(H.N[0]) * H.N[1] * H.N[2];
   const GridGeo G = geo_of(H, gp);
   const double inv_ntot = 1.0 / static_cast<double>(n);
-  T* rho = reinterpret_cast<T*>(P.gpe_rho);
-  T* phi = reinterpret_cast<T*>(P.gpe_phi);
+  T* rho = reinterpret_cast<T*>(P.gpe.rho);
+  T* phi = reinterpret_cast<T*>(P.gpe.phi);
   const T* Vext = reinterpret_cast<const T*>(gp.V_dev);
   // Case II time factor (1 - exp(-2 delta dt)) / (2 delta), dt in Case I; Case III: w carries it
   const bool loss = q > 0.0;
@@ -471,14 +506,14 @@ hipError_t run_ts_step(DevicePlan& P, const gpe_params& gp, double dt, double de
   return half_kinetic(psi_out);
 }
 
-template hipError_t run_gpe_energy_grad<double>(DevicePlan&, const gpe_params&, const Complex<double>*, double*,
-                                                Complex<double>*, hipStream_t);
-template hipError_t run_gpe_energy_grad<float>(DevicePlan&, const gpe_params&, const Complex<float>*, double*,
-                                               Complex<float>*, hipStream_t);
+template hipError_t run_gpe_energy_grad<double>(DevicePlan&, const GpeWork&, const gpe_params&,
+                                                const Complex<double>*, double*, Complex<double>*, hipStream_t);
+template hipError_t run_gpe_energy_grad<float>(DevicePlan&, const GpeWork&, const gpe_params&,
+                                               const Complex<float>*, double*, Complex<float>*, hipStream_t);
 template hipError_t run_gf_step<double>(DevicePlan&, const gpe_params&, double, int, const Complex<double>*,
-                                        Complex<double>*, hipStream_t);
+                                        Complex<double>*, double*, hipStream_t);
 template hipError_t run_gf_step<float>(DevicePlan&, const gpe_params&, double, int, const Complex<float>*,
-                                       Complex<float>*, hipStream_t);
+                                       Complex<float>*, double*, hipStream_t);
 template hipError_t run_ts_step<double>(DevicePlan&, const gpe_params&, double, double, double,
                                         const Complex<double>*, Complex<double>*, hipStream_t);
 template hipError_t run_ts_step<float>(DevicePlan&, const gpe_params&, double, double, double,

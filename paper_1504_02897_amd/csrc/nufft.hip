@@ -978,30 +978,47 @@ hipError_t run_apply(DevicePlan& P, const T* rho, T* phi, int sign, hipStream_t 
 
 // I_1 of the split (Eq. 3.9).  The box is zero-padded to the fine grid (2 N_i points,
 // k_m = 2 pi m / (2 N_i h_i)); the density enters without deconvolution.  Only the modes
-// m2 in [0, N2) are formed (a real field's half set; m2 = -N2 is a Nyquist plane): last-axis
+// m2 in [0, N2) are formed (a real field's half set; m2 = -N2 is a Nyquist plane).  3D: last-axis
 // FFT with padding, axis-1 FFT, then one pass that transforms axis 0, multiplies by
 // (1 - q) Uhat and transforms back, axis-1 inverse (front); last-axis inverse with truncation,
-// real part and accumulation into phi (back).  Works in fine_short.
+// real part and accumulation into phi (back).  2D (axes 1 and 2 of the internal layout): the
+// padded last-axis FFT, then the pass along axis 1 with the multiplier (front); the same last
+// pass (back).  Works in fine_short.
 template <typename T>
 hipError_t split_short_front(DevicePlan& P, const T* rho, hipStream_t s) {
   const HostTables& H = P.H;
-  if (!H.split || H.dim != 3 || !P.ones || !P.fine_short) return hipErrorInvalidValue;
+  if (!H.split || !P.ones || !P.fine_short) return hipErrorInvalidValue;
   C<T>* F = reinterpret_cast<C<T>*>(P.fine_short);
   const int nz = H.N[2];
-  const C<T>* tw0 = reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[0])]);
   const C<T>* tw1 = reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[1])]);
   const C<T>* tw2 = reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[2])]);
   SplitSymbol sp;
-  for (int i = 0; i < 3; ++i) {
-    sp.n[i] = H.nv[i];
-    sp.m[i] = H.mv[i];
-    sp.dk[i] = 2.0 * M_PI / (H.nf[i] * H.h[i]);
-  }
-  sp.nm = H.nv[0] * H.mv[0] + H.nv[1] * H.mv[1] + H.nv[2] * H.mv[2];
+  for (int i = 0; i < 3; ++i) sp.dk[i] = 2.0 * M_PI / (H.nf[i] * H.h[i]);
   sp.inv_s2 = 1.0 / (H.split_s * H.split_s);
+  sp.inv_s = 1.0 / H.split_s;
   sp.scale = 1.0 / (static_cast<double>(H.nf[0]) * H.nf[1] * H.nf[2]);
+  sp.dim = H.dim;
+  if (H.dim == 3) {
+    for (int i = 0; i < 3; ++i) {
+      sp.n[i] = H.nv[i];
+      sp.m[i] = H.mv[i];
+    }
+    sp.nm = H.nv[0] * H.mv[0] + H.nv[1] * H.mv[1] + H.nv[2] * H.mv[2];
+    sp.n3m3 = 0.0;
+  } else {
+    // the symbol pass runs along internal axis 1 (the paper's x) as the kernel's axis 0, with the
+    // last axis (the paper's y) as its axis 2
+    sp.n[0] = H.nv[0]; sp.n[1] = 0.0; sp.n[2] = H.nv[1];
+    sp.m[0] = H.mv[0]; sp.m[1] = 0.0; sp.m[2] = H.mv[1];
+    sp.dk[0] = sp.dk[1];
+    sp.dk[1] = 0.0;
+    sp.nm = 0.0;
+    sp.n3m3 = H.nv[2] * H.mv[2];
+  }
   DDI_CHECK((launch_contig<T, -1, R2C_PAD>(H.nf[2], rho, F, H.N[0], H.N[1], H.nf[0], H.nf[1], H.N[2], 0, nz, P.ones,
                                            P.ones, P.ones, tw2, s)));
+  if (H.dim == 2) return launch_symbol<T>(H.nf[1], F, 1, H.nf[2], H.N[1], nz, sp, tw1, s);
+  const C<T>* tw0 = reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[0])]);
   DDI_CHECK((launch_strided<T, -1>(H.nf[1], F, 1, H.nf[0], H.nf[1], H.nf[2], H.N[0], 1, H.N[1], 1, 0, H.N[1], 0, nz,
                                    tw1, s)));
   DDI_CHECK((launch_symbol<T>(H.nf[0], F, H.nf[1], H.nf[2], H.N[0], nz, sp, tw0, s)));
@@ -1013,7 +1030,7 @@ hipError_t split_short_front(DevicePlan& P, const T* rho, hipStream_t s) {
 template <typename T>
 hipError_t split_short_back(DevicePlan& P, T* phi, hipStream_t s) {
   const HostTables& H = P.H;
-  if (!H.split || H.dim != 3 || !P.ones || !P.fine_short) return hipErrorInvalidValue;
+  if (!H.split || !P.ones || !P.fine_short) return hipErrorInvalidValue;
   const C<T>* tw2 = reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[2])]);
   return launch_contig<T, 1, C2R_ADD>(H.nf[2], P.fine_short, phi, H.N[0], H.N[1], H.nf[0], H.nf[1], H.N[2], 0,
                                       H.N[2], P.ones, P.ones, P.ones, tw2, s);

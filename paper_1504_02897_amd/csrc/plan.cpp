@@ -50,7 +50,10 @@ void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
   }
 }
 
-// Exponential-of-semicircle kernel psi(z) = exp(beta (sqrt(1 - (2z/w)^2) - 1)), |z| < w/2.
+// Exponential-of-semicircle kernel psi(z) = exp(beta (sqrt(1 - (2z/w)^2) - 1)), |z| < w/2: the
+// spreading kernel of Barnett, Magland & af Klinteberg, "A parallel nonuniform fast Fourier
+// transform library based on an 'exponential of semicircle' kernel", SIAM J. Sci. Comput. 41(5),
+// C479-C504 (2019), with their shape parameter beta = 2.30 w for upsampling factor 2.
 double es_kernel(double z, int w, double beta) {
   double a = 2.0 * z / w;
   double s = 1.0 - a * a;
@@ -357,7 +360,6 @@ std::string build_tables(const ddi_params& p, HostTables& t, int* status) {
     if (!std::isfinite(p.stretch[a])) return "stretch must be finite";
 
   *status = DDI_ENOTSUP;
-  if (p.split && d != 3) return "the split of Eq. 3.9 is built for 3D only";
   // internal 3-axis layout: 2D grids live on axes 1 and 2
   const int off = 3 - d;
   for (int a = 0; a < 3; ++a) { t.N[a] = 1; t.nf[a] = 1; t.W[a] = 1; t.h[a] = 1.0; t.L[a] = 0.5; }
@@ -373,7 +375,7 @@ std::string build_tables(const ddi_params& p, HostTables& t, int* status) {
   }
   t.dim = d;
   t.w = w;
-  t.es_beta = 2.30 * w;
+  t.es_beta = 2.30 * w;     // the published choice for sigma = 2 (see es_kernel)
   t.cell = 1.0;
   for (int a = 0; a < 3; ++a) t.cell *= (a >= off ? t.h[a] : 1.0);
   if (d == 3) { t.tile[0] = 8; t.tile[1] = 8; t.tile[2] = kTileZ; }
@@ -488,8 +490,9 @@ std::string build_tables(const ddi_params& p, HostTables& t, int* status) {
         k_nat.push_back(k[0]);
         k_nat.push_back(k[1]);
         k_nat.push_back(k[2]);
-        // split: I_2 carries q(k) = exp(-|k|^2/s^2)
-        const double qk = t.split ? std::exp(-kk / (split_s * split_s)) : 1.0;
+        // split: I_2 carries q(k) = exp(-|k|^2/s^2) (3D) or erfc(|k|/s) (2D)
+        const double qk = !t.split ? 1.0
+                          : (d == 3 ? std::exp(-kk / (split_s * split_s)) : std::erfc(std::sqrt(kk) / split_s));
         c_nat.push_back(W * U * inv2pid * qk);
         base_nat.push_back(W * inv2pid * qk);
       }

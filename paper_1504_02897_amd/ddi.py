@@ -67,7 +67,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     for name in ("ddi_apply", "ddi_apply_adjoint", "ddi_type2", "ddi_type1"):
         getattr(lib, name).argtypes = [vp, vp, vp, vp]
     lib.gpe_energy_grad.argtypes = [vp, ctypes.POINTER(GPEParamsC), vp, ctypes.POINTER(f64), vp, vp]
-    lib.gpe_gf_step.argtypes = [vp, ctypes.POINTER(GPEParamsC), f64, i32, vp, vp, vp]
+    lib.gpe_gf_step.argtypes = [vp, ctypes.POINTER(GPEParamsC), f64, i32, vp, vp, vp, vp]
     lib.gpe_ts_step.argtypes = [vp, ctypes.POINTER(GPEParamsC), f64, f64, vp, vp, vp]
     lib.ddi_set_dipole.argtypes = [vp, ctypes.POINTER(f64), ctypes.POINTER(f64), vp]
     lib.gpe_ts_step_loss.argtypes = [vp, ctypes.POINTER(GPEParamsC), f64, f64, f64, vp, vp, vp]
@@ -136,7 +136,7 @@ class DDIPlan:
     dip_n, dip_m     dipole axes (dip_m None means m = n).
     quad             (n_rad, n_pol, n_azi); n_pol ignored in 2D.
     prec             "fp64" or "mixed".
-    split, split_s   the split of Eq. 3.9 (3D): Phi = I_1 + I_2, I_1 by the zero-padded FFT,
+    split, split_s   the split of Eq. 3.9 (3D and 2D): Phi = I_1 + I_2, I_1 by the zero-padded FFT,
                      I_2 over the ball of radius kmax (quad and kmax are then I_2's;
                      kmax = 0 and split_s = 0 select the defaults from tol and the box).
     stretch          per-axis factors of the quadrature (k = S k', weights times det S) for
@@ -257,12 +257,18 @@ class DDIPlan:
                                     _ptr(G) if grad else None, _stream()))
         return np.array(list(E)), G
 
-    def gf_step(self, psi, beta, lam, gamma=(1.0, 1.0, 1.0), dt=0.01, n_inner=1, V=None, out=None):
+    def gf_step(self, psi, beta, lam, gamma=(1.0, 1.0, 1.0), dt=0.01, n_inner=1, V=None, out=None,
+                residual=None):
+        """One gradient-flow step (gpe_gf_step); out may be psi.  residual: optional float64 CUDA
+        tensor of one element that receives max|out - psi| / dt (the stopping quantity)."""
         psi = self._grid(psi, complex_=True, name="psi")
         gp, V = self._gp(beta, lam, gamma, V)
         out = torch.empty_like(psi) if out is None else self._grid(out, complex_=True, name="out")
+        if residual is not None and (not isinstance(residual, torch.Tensor) or residual.device.type != "cuda"
+                                     or residual.dtype != torch.float64 or residual.numel() != 1):
+            raise TypeError("residual must be a float64 CUDA tensor of one element")
         _check(_lib.gpe_gf_step(self._h, ctypes.byref(gp), float(dt), int(n_inner), _ptr(psi), _ptr(out),
-                                _stream()))
+                                None if residual is None else _ptr(residual), _stream()))
         return out
 
     def ts_step(self, psi, beta, lam, gamma=(1.0, 1.0, 1.0), dt=0.001, delta=0.0, V=None, out=None):

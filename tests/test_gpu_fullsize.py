@@ -61,6 +61,41 @@ def test_full_apply_matches_stored_oracle(name):
     assert abs(np.linalg.norm(phi.ravel()) - gd["phi_l2"]) < 1e-12 * gd["phi_l2"]
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 1e-6)])
+def test_c2_full_grid_matches_oracle(prec, tol):
+    """The headline workload element by element over the whole 128^3 grid, in the launch
+    configuration the benchmark times: FP64 against the oracle on the same input, mixed against
+    the FP64 oracle on the FP32-rounded input (the oracle's direct sums take about 40 s here)."""
+    say(f"case: c2_128 full-grid apply {prec} vs oracle computed here")
+    name = "c2_128"
+    wl = I.WORKLOADS[name]
+    d = I.mixture_workload(name, seed=0)
+    plan = workload_plan(name, d["dip_n"], prec=prec)
+    rho = d["rho"] if prec == "fp64" else d["rho"].astype(np.float32).astype(np.float64)
+    phi = plan.apply(torch.from_numpy(rho).to(DEV, plan.real_dtype)).double().cpu().numpy()
+    prob = O.DDIProblem(dim=3, n=wl["n"], L=wl["L"], dip_n=tuple(d["dip_n"]), n_rad=wl["quad"][0],
+                        n_pol=wl["quad"][1], n_azi=wl["quad"][2])
+    ref = O.ddi_apply(rho, prob)
+    err = float(np.max(np.abs(phi - ref)) / np.max(np.abs(ref)))
+    say(f"  rel Linf over all 128^3 points = {err:.3e}; rel l2 = {O.rel_l2(phi, ref):.3e}")
+    assert err < tol
+
+
+def test_c4_mixed_composed_apply_sampled_points():
+    """The 256^3 mixed operator as a whole (type-2, weights, type-1) at stored sampled points: the
+    oracle's rhohat at all 655,096 nodes of the FP32-rounded density and the pointwise type-1
+    sum (tests/golden/make_golden.py); error relative to max|Phi| over the grid."""
+    say("case: c4_256 mixed composed apply at stored points")
+    gd = golden("c4_256")
+    d = I.mixture_workload("c4_256", seed=0)
+    plan = workload_plan("c4_256", gd["dip_n"])
+    phi = plan.apply(torch.from_numpy(d["rho"]).to(DEV, torch.float32)).double().cpu().numpy()
+    got = np.array([phi[tuple(p)] for p in gd["points"]])
+    err = float(np.max(np.abs(got - np.array(gd["phi"])))) / float(np.max(np.abs(phi)))
+    say(f"  sampled rel err (to max|Phi|) = {err:.3e} at {len(got)} points")
+    assert err < 1e-6
+
+
 @pytest.mark.parametrize("name,tol", [("c2_128", 1e-13), ("c3_512", 1e-13), ("c4_256", 1e-6)])
 def test_full_type2_matches_stored_oracle(name, tol):
     say(f"case: {name} full-size type-2 at sampled nodes")

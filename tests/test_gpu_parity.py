@@ -403,8 +403,88 @@ def test_gpe_mixed_energy():
     psi32 = psi.astype(np.complex64)
     E, G = plan.energy_grad(to_dev(psi32, torch.complex64), gp.beta, gp.lam, gp.gamma)
     E_or, G_or = O.gpe_energy_grad(psi32.astype(np.complex128), prob, gp)
-    assert np.max(np.abs(E - E_or)) < 1e-6 * np.max(np.abs(E_or))
-    assert relinf(G.cpu().numpy(), G_or) < 1e-5
+    e_E = float(np.max(np.abs(E - E_or)) / np.max(np.abs(E_or)))
+    e_G = relinf(G.cpu().numpy(), G_or)
+    say(f"  energies rel {e_E:.3e}, gradient rel Linf {e_G:.3e}")
+    assert e_E < MIXED_TOL
+    assert e_G < MIXED_TOL
+
+
+@pytest.mark.parametrize("n_inner", [0, 3])
+def test_gf_step_mixed_matches_oracle(n_inner):
+    """Mixed gradient-flow step (FP32 grids, FP64 reductions) against the FP64 oracle step on the
+    FP32-rounded input, out of place and in place; the stopping residual it returns against the
+    change of the stored values."""
+    say(f"case: gf step 16^3 mixed n_inner {n_inner}")
+    plan, prob, psi, gp = gpe_case(prec="mixed")
+    psi32 = psi.astype(np.complex64)
+    x = to_dev(psi32, torch.complex64)
+    res = torch.zeros(1, dtype=torch.float64, device=DEV)
+    out = plan.gf_step(x, gp.beta, gp.lam, gp.gamma, dt=0.01, n_inner=n_inner, residual=res)
+    ref = O.gf_step(psi32.astype(np.complex128), prob, gp, dt=0.01, n_inner=n_inner)
+    err = relinf(out.cpu().numpy().astype(np.complex128), ref)
+    say(f"  rel Linf = {err:.3e}")
+    assert err < MIXED_TOL
+    change = float((out.to(torch.complex128) - x.to(torch.complex128)).abs().max()) / 0.01
+    assert abs(float(res[0]) - change) <= 1e-12 * change
+    y = x.clone()
+    plan.gf_step(y, gp.beta, gp.lam, gp.gamma, dt=0.01, n_inner=n_inner, out=y)
+    torch.cuda.synchronize()
+    assert torch.equal(y, out)
+
+
+def test_gf_step_residual_fp64():
+    """gpe_gf_step's stopping residual max|out - in| / dt, out of place and in place (where the
+    input is overwritten as the residual is formed)."""
+    say("case: gf step residual 16^3 fp64")
+    plan, prob, psi, gp = gpe_case()
+    x = to_dev(psi, torch.complex128)
+    res = torch.zeros(1, dtype=torch.float64, device=DEV)
+    out = plan.gf_step(x, gp.beta, gp.lam, gp.gamma, dt=0.02, n_inner=2, residual=res)
+    change = float((out - x).abs().max()) / 0.02
+    assert abs(float(res[0]) - change) <= 1e-13 * change
+    y = x.clone()
+    res2 = torch.zeros(1, dtype=torch.float64, device=DEV)
+    plan.gf_step(y, gp.beta, gp.lam, gp.gamma, dt=0.02, n_inner=2, out=y, residual=res2)
+    torch.cuda.synchronize()
+    assert torch.equal(y, out) and float(res2[0]) == float(res[0])
+    with pytest.raises(TypeError):
+        plan.gf_step(x, gp.beta, gp.lam, gp.gamma, dt=0.02, residual=torch.zeros(1, device=DEV))
+
+
+def test_2d_mixed_apply_adjoint_and_halves():
+    """2D mixed precision (the Kahan-compensated FP32 spread of the 2D path, FP32 FFTs and
+    interpolation, FP64 tables) on a C3-shaped input (mixture + noise, n tilted 45 degrees):
+    apply, adjoint, type-2 and type-1 against the FP64 oracle on the FP32-rounded input."""
+    say("case: 2D 128^2 mixed, mixture + noise")
+    n, L = (128, 128), (8.0, 8.0)
+    plan, prob = make(2, n, L, (64, 1, 128), dip_n=(math.sqrt(0.5), 0.0, math.sqrt(0.5)), prec="mixed")
+    lumps, rng = I.mixture_lumps(7, 2, (1, 6))
+    psi = I.lumps_on_grid(lumps, n, L)
+    psi = psi + 0.1 * np.max(np.abs(psi)) * rng.uniform(0, 1, n) * np.exp(1j * rng.uniform(0, 2 * np.pi, n))
+    psi, _ = I.normalise(psi, n, L)
+    rho32 = (np.abs(psi) ** 2).astype(np.float32)
+    r64 = rho32.astype(np.float64)
+    phi = plan.apply(to_dev(rho32, torch.float32)).cpu().numpy().astype(np.float64)
+    err = relinf(phi, O.ddi_apply(r64, prob))
+    say(f"  apply rel Linf = {err:.3e}")
+    assert err < MIXED_TOL
+    sig32 = I.random_field(12, n).astype(np.float32)
+    adj = plan.apply_adjoint(to_dev(sig32, torch.float32)).cpu().numpy().astype(np.float64)
+    erra = relinf(adj, O.ddi_apply_adjoint(sig32.astype(np.float64), prob))
+    say(f"  adjoint rel Linf = {erra:.3e}")
+    assert erra < MIXED_TOL
+    rows, quad, _ = oracle_rows(plan, prob)
+    rh = plan.type2(to_dev(rho32, torch.float32)).cpu().numpy().astype(np.complex128)
+    ref2 = O.rhohat(r64, prob, quad.k[rows])
+    err2 = float(np.max(np.abs(rh - ref2)) / np.max(np.abs(ref2)))
+    say(f"  type2 rel Linf = {err2:.3e}")
+    assert err2 < MIXED_TOL
+    g = (I.random_field(13, (plan.m_eff,)) + 1j * I.random_field(14, (plan.m_eff,))).astype(np.complex64)
+    phi1 = plan.type1(to_dev(g, torch.complex64)).cpu().numpy().astype(np.float64)
+    err1 = relinf(phi1, O.nodes_to_grid(g.astype(np.complex128), prob, quad.k[rows]))
+    say(f"  type1 rel Linf = {err1:.3e}")
+    assert err1 < MIXED_TOL
 
 
 # ---------------------------------------------------------------- error paths

@@ -1,4 +1,4 @@
-"""The split of Eq. 3.9 (Phi = I_1 + I_2, 3D) on the HIP path, through the C ABI.
+"""The split of Eq. 3.9 (Phi = I_1 + I_2, 3D and 2D) on the HIP path, through the C ABI.
 
 Element by element against the oracle's split on the same seeded input: FP64 rel Linf
 <= 1e-12; mixed rel Linf <= 1e-6 against the FP64 oracle on the FP32-rounded input.  The
@@ -144,11 +144,6 @@ def test_split_128_matches_exact_gaussian_ddi():
     assert err < 1e-11
 
 
-def test_split_rejected_in_2d():
-    with pytest.raises(DDIError):
-        DDIPlan(2, (64, 64), (8.0, 8.0), quad=(16, 1, 32), split=True)
-
-
 def test_split_c2_mixture_matches_exact_ddi():
     """The benchmark's split configuration on the c2_128 input (|psi|^2 of four seeded lumps, which
     expands into Gaussian products, Ex. 2.3) against the exact DDI at sampled points."""
@@ -237,3 +232,97 @@ def test_split_parameter_defaults():
     rho = I.c1_density(n, L)
     phi = q.apply(to_dev(rho, torch.float64)).cpu().numpy()
     assert relinf(phi, O.split_apply(rho, prob, 0.8)) <= FP64_TOL
+
+
+# ---------------------------------------------------------------- the split in 2D
+CASES_2D = [
+    # (n, L, quad, dip_n, dip_m, density)
+    ((128, 128), (16.0, 16.0), (32, 1, 64), (0.0, -0.896, 0.44404), (0.0, -0.52476, 0.85125), "gauss"),
+    ((64, 128), (8.0, 16.0), (24, 1, 48), (0.6, 0.0, 0.8), None, "random"),
+    ((512, 512), (16.0, 16.0), (32, 1, 64), (math.sqrt(0.5), 0.0, math.sqrt(0.5)), None, "c3"),
+]
+
+
+def make_split_2d(n, L, quad, dip_n, dip_m=None, prec="fp64"):
+    tol = 1e-13 if prec == "fp64" else 1e-7
+    plan = DDIPlan(2, n, L, dip_n=dip_n, dip_m=dip_m, quad=quad, prec=prec, tol=tol, split=True)
+    s, R2 = O.split_defaults(L, tol)
+    assert plan.info["split"]
+    assert abs(plan.info["split_s"] - s) <= 1e-14 * s and abs(plan.info["kmax"] - R2) <= 1e-14 * R2
+    prob = O.DDIProblem(dim=2, n=tuple(n), L=tuple(L), dip_n=tuple(dip_n),
+                        dip_m=None if dip_m is None else tuple(dip_m), n_rad=quad[0], n_pol=1, n_azi=quad[2],
+                        kmax=R2)
+    return plan, prob, s
+
+
+def density_2d(kind, n, L):
+    if kind == "gauss":
+        return I.gaussian_density(n, L, math.sqrt(1.3))
+    if kind == "c3":
+        return I.mixture_workload("c3_512", seed=0)["rho"]
+    return I.random_field(12, n) ** 2
+
+
+@pytest.mark.parametrize("case", CASES_2D, ids=lambda c: "x".join(map(str, c[0])) + "_" + c[5])
+def test_split_2d_fp64_matches_oracle(case):
+    """Eq. 3.9 in 2D (q = erfc(|k|/s)): apply and the literal adjoint against the oracle's split
+    element by element (FP64 bar); on the Table 3 Gaussian also against the exact DDI of Ex. 2.2."""
+    n, L, quad, dn, dm, kind = case
+    say(f"case: 2D split fp64 {n} {kind}")
+    plan, prob, s = make_split_2d(n, L, quad, dn, dm)
+    rho = density_2d(kind, n, L)
+    phi = plan.apply(to_dev(rho, torch.float64)).cpu().numpy()
+    ref = O.split_apply(rho, prob, s)
+    err = relinf(phi, ref)
+    say(f"  rel Linf vs oracle split = {err:.3e} (M_eff {plan.m_eff})")
+    assert err < FP64_TOL
+    sig = I.random_field(13, n)
+    adj = plan.apply_adjoint(to_dev(sig, torch.float64)).cpu().numpy()
+    k, c = O.split_long_range_nodes(prob, s)
+    ref_a = O.split_short_range(sig, prob, s) + O.nodes_to_grid(c * O.rhohat(sig, prob, k, sign=+1.0), prob, k,
+                                                                 sign=-1.0)
+    erra = relinf(adj, ref_a)
+    say(f"  adjoint rel Linf = {erra:.3e}")
+    assert erra < FP64_TOL
+    if kind == "gauss":
+        x, y = np.meshgrid(*I.grid_axes(n, L), indexing="ij")
+        e_h = O.rel_l2(phi, R.phi_gaussian_2d(x, y, math.sqrt(1.3), dn, dm))
+        say(f"  e_h vs Ex. 2.2 = {e_h:.3e} (Table 3, L = 16, h = 1/4: 3.489e-14)")
+        assert e_h < 1e-13
+
+
+def test_split_2d_mixed_matches_oracle():
+    say("case: 2D split mixed 512^2 c3 input")
+    n, L = (512, 512), (16.0, 16.0)
+    plan, prob, s = make_split_2d(n, L, (16, 1, 32), (math.sqrt(0.5), 0.0, math.sqrt(0.5)), prec="mixed")
+    rho32 = I.mixture_workload("c3_512", seed=0)["rho"].astype(np.float32)
+    phi = plan.apply(to_dev(rho32, torch.float32)).cpu().numpy().astype(np.float64)
+    err = relinf(phi, O.split_apply(rho32.astype(np.float64), prob, s))
+    say(f"  rel Linf = {err:.3e}")
+    assert err < MIXED_TOL
+
+
+def test_split_2d_set_dipole_and_gpe():
+    """A new axis on a 2D split plan (I_1 takes it, I_2's coefficients are re-evaluated), and the GPE
+    energy and gradient on the split operator against the oracle (its energy takes the operator)."""
+    say("case: 2D split set_dipole + GPE energy 64^2")
+    n, L = (64, 64), (8.0, 8.0)
+    plan, prob, s = make_split_2d(n, L, (24, 1, 48), (0.0, 0.0, 1.0))
+    nv = (0.6, 0.0, 0.8)
+    plan.set_dipole(nv)
+    prob.dip_n = nv
+    prob._cache.clear()
+    lumps, _ = I.mixture_lumps(2, 2, (2, 3), centre=1.0, widths=(0.8, 1.5))
+    psi, _ = I.normalise(I.lumps_on_grid(lumps, n, L), n, L)
+    rho = np.abs(psi) ** 2
+    phi = plan.apply(to_dev(rho, torch.float64)).cpu().numpy()
+    assert relinf(phi, O.split_apply(rho, prob, s)) < FP64_TOL
+    gp = O.GPEParams(beta=10.0, lam=8.0, gamma=(1.0, 1.5))
+    E, G = plan.energy_grad(to_dev(psi, torch.complex128), gp.beta, gp.lam, gp.gamma)
+    k, c = O.split_long_range_nodes(prob, s)
+    A = lambda r: O.split_apply(r, prob, s)                                         # noqa: E731
+    At = lambda r: O.split_short_range(r, prob, s) + O.nodes_to_grid(               # noqa: E731
+        c * O.rhohat(r, prob, k, sign=+1.0), prob, k, sign=-1.0)
+    E_or, G_or = O.gpe_energy_grad(psi, prob, gp, ops=(A, At))
+    assert np.max(np.abs(E - E_or)) < 1e-12 * np.max(np.abs(E_or))
+    assert relinf(G.cpu().numpy(), G_or) < FP64_TOL

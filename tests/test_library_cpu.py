@@ -88,7 +88,6 @@ def _params(**kw):
     (dict(prec=7), 1),
     (dict(split=2), 1),
     (dict(split=1, split_s=float("inf")), 1),
-    (dict(split=1, dim=2, n=(64, 64)), 4),    # the split is built for 3D only
     (dict(stretch=(1.0, float("nan"), 1.0)), 1),
 ])
 def test_invalid_plans_are_rejected_before_device_use(lib, bad, code):

@@ -81,6 +81,11 @@ CASES = {
     # a small ball whose supports end on the last position of a tile: the axis-1 window is tight
     "3d_split_64": (dict(dim=3, n=(64, 64, 64), L=(8.0,) * 3, quad=(12, 12, 24), tol=1e-13, split=True, split_s=1.5),
                     dict(dim=3, n=(64, 64, 64), L=(8.0,) * 3, n_rad=12, n_pol=12, n_azi=24)),
+    # the 2D split: I_2 weights times erfc(|k|/s) on the small polar ball
+    "2d_split": (dict(dim=2, n=(128, 128), L=(16.0, 16.0), dip_n=(0.0, -0.896, 0.44404),
+                      dip_m=(0.0, -0.52476, 0.85125), quad=(32, 1, 64), tol=1e-13, split=True),
+                 dict(dim=2, n=(128, 128), L=(16.0, 16.0), dip_n=(0.0, -0.896, 0.44404),
+                      dip_m=(0.0, -0.52476, 0.85125), n_rad=32, n_pol=1, n_azi=64)),
 }
 
 
