@@ -209,6 +209,24 @@ ddi_status gpe_energy_grad(ddi_plan_t plan, const gpe_params* gp, const void* ps
                            double E_out[5], void* grad_dev, void* stream);
 
 /*
+ * gpe_energy_grad for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  The same energies and gradient as
+ * gpe_energy_grad, with its GPE workspace (three real grids, one complex grid and the reduction
+ * partials of the plan's grid) taken from a static device array of 96 MiB that the library holds
+ * on every GPU it runs on until the process ends, instead of the plan's own workspace.
+ *   E_dev      device pointer to 5 doubles (kin, pot, int, dip, total), written on `stream`;
+ *   grad_dev   as in gpe_energy_grad (nullable).
+ * Allocates nothing (no hipMalloc, hipFree or allocating library call) and does not synchronise.
+ * A grid whose workspace exceeds 96 MiB (20 bytes per point in mixed precision, 40 in FP64 plus the
+ * partials: up to about 2.4M points in FP64, e.g. 128^3, and 4.8M in mixed) is rejected with
+ * DDI_EINVAL before any work.  Every call on a GPU shares that GPU's array: calls that overlap on
+ * one GPU (different streams, or different host threads) race and must be ordered by the caller.
+ * Nothing in the array needs to start at zero: every call writes each part before reading it.
+ */
+ddi_status gpe_energy_grad_noalloc(ddi_plan_t plan, const gpe_params* gp, const void* psi_dev, double* E_dev,
+                                   void* grad_dev, void* stream);
+
+/*
  * One step of the gradient flow with discrete normalisation (Sec. 3.1,
  * Eqs. gf-eq2, gf-colb2, gffg33): Phi^n = A |psi_in|^2 once, then n_inner
  * stabilised Fourier iterations for (1/dt - 1/2 Lap + B) phi1 = psi_in/dt,

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -194,6 +195,54 @@ ddi_status ts_step_impl(ddi_plan_t plan, const gpe_params& gp, double dt, double
                          : ddi::run_ts_step<double>(P, gp, dt, delta, q, static_cast<const ddi::Complex<double>*>(in),
                                                     static_cast<ddi::Complex<double>*>(out), s);
   if (e != hipSuccess) return hip_fail(e, what);
+  return DDI_OK;
+}
+
+// Static workspace of gpe_energy_grad_noalloc: one copy of this array per GPU, resident from the
+// module's load until the process ends.  Host code never uses the array's name as an address:
+// each device's copy is located once with hipGetSymbolAddress and only that pointer is used.
+constexpr size_t kScratchBytes = size_t(96) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of the current device's copy of `scratch` (looked up on the first call per
+// device, with that device current).
+ddi_status scratch_address(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(DDI_ENOTSUP, "device index beyond the static workspace table");
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) return fail(DDI_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return DDI_OK;
+}
+
+// Carves the GPE workspace of an n-point grid of real type T out of a static workspace of
+// kScratchBytes at base (256-byte aligned pieces); fails if it does not fit.
+template <typename T>
+ddi_status scratch_gpe_work(const ddi::DevicePlan& P, void* base, ddi::GpeWork& W) {
+  const int64_t n = static_cast<int64_t>(P.H.N[0]) * P.H.N[1] * P.H.N[2];
+  const int nb = ddi::gpe_reduction_blocks<T>(P);
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t real = up(n * sizeof(T)), cplx = up(n * sizeof(ddi::Complex<T>));
+  const size_t need = 3 * real + cplx + up(ddi::gpe_red_doubles(nb) * sizeof(double));
+  if (need > kScratchBytes)
+    return fail(DDI_EINVAL, "gpe_energy_grad_noalloc: the grid needs " + std::to_string(need) +
+                                " bytes of workspace, the static workspace holds " + std::to_string(kScratchBytes));
+  unsigned char* b = static_cast<unsigned char*>(base);
+  W.rho = b;
+  W.phi = b + real;
+  W.phit = b + 2 * real;
+  W.c1 = b + 3 * real;
+  W.c2 = nullptr;
+  W.red = reinterpret_cast<double*>(b + 3 * real + cplx);
+  W.red_blocks = nb;
   return DDI_OK;
 }
 
@@ -493,6 +542,28 @@ ddi_status gpe_energy_grad(ddi_plan_t plan, const gpe_params* gp, const void* ps
   if (e != hipSuccess) return hip_fail(e, "gpe_energy_grad launch");
   HIP_TRY(hipMemcpyAsync(E_out, E_dev, 5 * sizeof(double), hipMemcpyDeviceToHost, s), "copy energies");
   HIP_TRY(hipStreamSynchronize(s), "gpe_energy_grad");
+  return DDI_OK;
+}
+
+ddi_status gpe_energy_grad_noalloc(ddi_plan_t plan, const gpe_params* gp, const void* psi_dev, double* E_dev,
+                                   void* grad_dev, void* stream) {
+  ddi_status st = check_plan(plan);
+  if (st != DDI_OK) return st;
+  if (!gp || !psi_dev || !E_dev) return fail(DDI_EINVAL, "NULL argument");
+  if (!std::isfinite(gp->beta) || !std::isfinite(gp->lambda)) return fail(DDI_EINVAL, "beta and lambda must be finite");
+  ddi::DevicePlan& P = plan->P;
+  void* base = nullptr;
+  st = scratch_address(P.device, &base);
+  if (st != DDI_OK) return st;
+  ddi::GpeWork W;
+  st = P.mixed ? scratch_gpe_work<float>(P, base, W) : scratch_gpe_work<double>(P, base, W);
+  if (st != DDI_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = P.mixed ? ddi::run_gpe_energy_grad<float>(P, W, *gp, static_cast<const ddi::Complex<float>*>(psi_dev), E_dev,
+                                                           static_cast<ddi::Complex<float>*>(grad_dev), s)
+                         : ddi::run_gpe_energy_grad<double>(P, W, *gp, static_cast<const ddi::Complex<double>*>(psi_dev), E_dev,
+                                                            static_cast<ddi::Complex<double>*>(grad_dev), s);
+  if (e != hipSuccess) return hip_fail(e, "gpe_energy_grad_noalloc launch");
   return DDI_OK;
 }
 

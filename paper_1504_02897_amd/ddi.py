@@ -53,6 +53,7 @@ class PlanInfo(ctypes.Structure):
 
 
 EXPORTED = ["ddi_plan", "ddi_apply", "ddi_apply_adjoint", "ddi_type2", "ddi_type1", "gpe_energy_grad",
+            "gpe_energy_grad_noalloc",
             "gpe_gf_step", "gpe_ts_step", "gpe_ts_step_loss", "ddi_set_dipole", "ddi_profile_apply", "ddi_plan_info", "ddi_plan_nodes", "ddi_destroy", "ddi_last_error"]
 STAGES = ["fft_last_pad", "fft_axis1_t2", "fft_axis0_t2", "interp", "spread", "spread_reduce", "fft_axis0_t1",
           "fft_axis1_t1", "fft_last_trunc"]
@@ -67,6 +68,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     for name in ("ddi_apply", "ddi_apply_adjoint", "ddi_type2", "ddi_type1"):
         getattr(lib, name).argtypes = [vp, vp, vp, vp]
     lib.gpe_energy_grad.argtypes = [vp, ctypes.POINTER(GPEParamsC), vp, ctypes.POINTER(f64), vp, vp]
+    lib.gpe_energy_grad_noalloc.argtypes = [vp, ctypes.POINTER(GPEParamsC), vp, vp, vp, vp]
     lib.gpe_gf_step.argtypes = [vp, ctypes.POINTER(GPEParamsC), f64, i32, vp, vp, vp, vp]
     lib.gpe_ts_step.argtypes = [vp, ctypes.POINTER(GPEParamsC), f64, f64, vp, vp, vp]
     lib.ddi_set_dipole.argtypes = [vp, ctypes.POINTER(f64), ctypes.POINTER(f64), vp]
@@ -256,6 +258,24 @@ class DDIPlan:
         _check(_lib.gpe_energy_grad(self._h, ctypes.byref(gp), _ptr(psi), E,
                                     _ptr(G) if grad else None, _stream()))
         return np.array(list(E)), G
+
+    def energy_grad_noalloc(self, psi, beta, lam, gamma=(1.0, 1.0, 1.0), V=None, E_out=None, grad_out=None,
+                            grad=True):
+        """The same energies and gradient through gpe_energy_grad_noalloc, which allocates nothing and
+        does not synchronise: E_out (float64 CUDA tensor of 5) and grad_out (or new tensors) receive
+        them on the current stream.  Returns (E_out, G or None)."""
+        psi = self._grid(psi, complex_=True, name="psi")
+        gp, V = self._gp(beta, lam, gamma, V)
+        if E_out is None:
+            E_out = torch.empty(5, dtype=torch.float64, device=psi.device)
+        elif E_out.device.type != "cuda" or E_out.dtype != torch.float64 or E_out.numel() != 5 or not E_out.is_contiguous():
+            raise TypeError("E_out must be a contiguous float64 CUDA tensor of 5 elements")
+        G = None
+        if grad:
+            G = torch.empty_like(psi) if grad_out is None else self._grid(grad_out, complex_=True, name="grad_out")
+        _check(_lib.gpe_energy_grad_noalloc(self._h, ctypes.byref(gp), _ptr(psi), _ptr(E_out),
+                                            _ptr(G) if grad else None, _stream()))
+        return E_out, G
 
     def gf_step(self, psi, beta, lam, gamma=(1.0, 1.0, 1.0), dt=0.01, n_inner=1, V=None, out=None,
                 residual=None):
