@@ -65,8 +65,10 @@ typedef enum { DDI_FP64 = 0, DDI_MIXED = 1 } ddi_precision;
 /*
  * Plan parameters (Sec. 2.1).
  *  dim          2 or 3.
- *  n[3]         grid points per axis (n[2] ignored for dim 2); powers of two,
- *               8 <= n <= 512 in 3D, 32 <= n <= 512 in 2D.
+ *  n[3]         grid points per axis (n[2] ignored for dim 2); powers of two or
+ *               three times a power of two (e.g. 96), 8 <= n <= 512 in 3D,
+ *               32 <= n <= 512 in 2D, and in 2D a first axis of the form 3 * 2^a
+ *               must be at least 96 (its oversampled axis holds whole 64-point tiles).
  *  L[3]         half box lengths; the box is [-L_i, L_i), h_i = 2 L_i / n_i.
  *  dip_n[3]     unit dipole axis n, used as given (not renormalised; must be
  *               non-zero and finite).

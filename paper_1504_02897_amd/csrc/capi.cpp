@@ -11,6 +11,7 @@
 
 #include "alloc_group.h"
 #include "ddi_internal.h"
+#include "fft.h"
 
 struct ddi_plan_s {
   ddi::DevicePlan P;
@@ -121,12 +122,11 @@ ddi_status build_device(ddi::DevicePlan& P, hipStream_t s, std::vector<ddi::Node
     P.pads = dp;
   }
   // twiddles for every FFT length used: fine grid sizes and the unpadded sizes
-  tws.assign(11, {});
+  tws.assign(ddi::kTwSlots, {});
   for (int a = 0; a < 3; ++a) {
     for (int n : {H.nf[a], H.N[a]}) {
       if (n < 2) continue;
-      int l = 0;
-      while ((1 << l) < n) ++l;
+      const int l = ddi::tw_slot(n);
       if (P.twiddles[l]) continue;
       std::vector<double> t = ddi::twiddle_table(n);
       tws[l].resize(n);

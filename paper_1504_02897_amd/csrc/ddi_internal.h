@@ -12,6 +12,7 @@
 namespace ddi {
 
 constexpr int kWMax = 16;          // largest kernel width
+constexpr int kTwSlots = 20;       // twiddle tables: lengths 2^0..2^10 and 3 * 2^0..3 * 2^8
 constexpr int kTileZ = 8;          // spread tile extent along the last axis (registers per lane)
 #ifndef DDI_INTERP_BLOCK3
 #define DDI_INTERP_BLOCK3 4
@@ -68,6 +69,7 @@ constexpr bool kInterpMfma = DDI_INTERP_MFMA != 0;
 #endif
 // spread on the matrix cores where the plan has row windows
 constexpr bool kSpreadMfma = DDI_SPREAD_MFMA != 0;
+
 
 // One quadrature node as seen by the spread / interpolation kernels: the first
 // fine-grid index of its support on each axis (already reduced mod n_fine) and
@@ -260,7 +262,7 @@ struct DevicePlan {
     int32_t* ent = nullptr;
   } dsched[2];
   bool interp_lds_ready = false;
-  void* twiddles[11] = {};       // per log2(n): Complex<T>[n]
+  void* twiddles[kTwSlots] = {}; // per FFT length n (slot tw_slot(n) of fft.h): Complex<T>[n]
   // workspace
   void* fine = nullptr;          // Complex<T>[nf0*nf1*nf2]
   void* gnodes = nullptr;        // Complex<T>[M]

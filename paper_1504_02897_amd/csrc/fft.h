@@ -64,4 +64,8 @@ inline int ilog2(int n) {
   return l;
 }
 
+// Slot of the twiddle table of an FFT length: n = 2^a (a <= 10) at slot a, n = 3 * 2^a
+// (a <= 8) at slot 11 + a.
+inline int tw_slot(int n) { return n % 3 == 0 ? 11 + ilog2(n / 3) : ilog2(n); }
+
 }  // namespace ddi

@@ -12,85 +12,50 @@
 #include <type_traits>
 
 #include "fft.h"
+#include "fft_regs.h"
 
 namespace ddi {
 
-template <typename T>
-using C = Complex<T>;
-
-template <typename T>
-__device__ __forceinline__ C<T> cmul(C<T> a, C<T> b) {
-  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
-}
-template <typename T>
-__device__ __forceinline__ C<T> cadd(C<T> a, C<T> b) { return {a.re + b.re, a.im + b.im}; }
-template <typename T>
-__device__ __forceinline__ C<T> csub(C<T> a, C<T> b) { return {a.re - b.re, a.im - b.im}; }
-
-// cos(2 pi j / 16) from the first-quadrant values
-__host__ __device__ constexpr double cos_16(int j) {
-  j &= 15;
-  const double q[5] = {1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173, 0.0};
-  return j <= 4 ? q[j] : (j <= 8 ? -q[8 - j] : (j <= 12 ? -q[j - 8] : q[16 - j]));
-}
-
-// ------------------------------------------------------------------ in-register DFT of size R <= 16
-// out[k] = sum_r v[r] exp(SIGN 2 pi i r k / R), iterative radix-2 decimation in time.
-template <int R>
-__device__ __forceinline__ constexpr int bitrev(int i) {
-  int r = 0;
-  for (int b = 1; b < R; b <<= 1) { r = (r << 1) | (i & 1); i >>= 1; }
-  return r;
-}
-
-template <typename T, int R, int SIGN>
-__device__ __forceinline__ void dft_regs(C<T>* v) {
-#pragma unroll
-  for (int i = 0; i < R; ++i) {
-    const int j = bitrev<R>(i);
-    if (j > i) { C<T> t = v[i]; v[i] = v[j]; v[j] = t; }
-  }
-#pragma unroll
-  for (int m = 2; m <= R; m <<= 1) {
-#pragma unroll
-    for (int k = 0; k < R; k += m) {
-#pragma unroll
-      for (int j = 0; j < m / 2; ++j) {
-        const int idx = j * (16 / m);      // angle index in units of 2 pi / 16, in [0, 8)
-        C<T> b = v[k + j + m / 2];
-        C<T> t;
-        if (idx == 0) {
-          t = b;
-        } else if (idx == 4) {             // exp(SIGN i pi/2) = SIGN i
-          t = SIGN > 0 ? C<T>{-b.im, b.re} : C<T>{b.im, -b.re};
-        } else {
-          const T c = static_cast<T>(cos_16(idx));
-          const T s = static_cast<T>(SIGN * cos_16(idx - 4));
-          t = {b.re * c - b.im * s, b.re * s + b.im * c};
-        }
-        C<T> a = v[k + j];
-        v[k + j] = cadd(a, t);
-        v[k + j + m / 2] = csub(a, t);
-      }
-    }
-  }
-}
+#ifndef DDI_STRIDED_SEG
+#define DDI_STRIDED_SEG 128
+#endif
+#ifndef DDI_STRIDED_THREADS
+#define DDI_STRIDED_THREADS 1024
+#endif
+#ifndef DDI_CONTIG_THREADS
+#define DDI_CONTIG_THREADS 256
+#endif
+// Launch shapes (measured optima): strided passes bundle lines until a row segment along the last
+// axis has kStridedSeg bytes (at most kStridedThreads threads); contiguous passes run
+// kContigThreads threads per workgroup.
+constexpr int kStridedSeg = DDI_STRIDED_SEG;
+constexpr int kStridedThreads = DDI_STRIDED_THREADS;
+constexpr int kContigThreads = DDI_CONTIG_THREADS;
 
 // ------------------------------------------------------------------ radix plans
 template <int N> struct RadixPlan;
-template <> struct RadixPlan<8> { static constexpr int R1 = 8, R2 = 1, R3 = 1; };
-template <> struct RadixPlan<16> { static constexpr int R1 = 4, R2 = 4, R3 = 1; };
-template <> struct RadixPlan<32> { static constexpr int R1 = 8, R2 = 4, R3 = 1; };
-template <> struct RadixPlan<64> { static constexpr int R1 = 8, R2 = 8, R3 = 1; };
-template <> struct RadixPlan<128> { static constexpr int R1 = 16, R2 = 8, R3 = 1; };
-template <> struct RadixPlan<256> { static constexpr int R1 = 16, R2 = 16, R3 = 1; };
-template <> struct RadixPlan<512> { static constexpr int R1 = 8, R2 = 8, R3 = 8; };
-template <> struct RadixPlan<1024> { static constexpr int R1 = 16, R2 = 16, R3 = 4; };
+template <> struct RadixPlan<8> { static constexpr int R1 = 8, R2 = 1, R3 = 1, R4 = 1; };
+template <> struct RadixPlan<16> { static constexpr int R1 = 4, R2 = 4, R3 = 1, R4 = 1; };
+template <> struct RadixPlan<32> { static constexpr int R1 = 8, R2 = 4, R3 = 1, R4 = 1; };
+template <> struct RadixPlan<64> { static constexpr int R1 = 8, R2 = 8, R3 = 1, R4 = 1; };
+template <> struct RadixPlan<128> { static constexpr int R1 = 16, R2 = 8, R3 = 1, R4 = 1; };
+template <> struct RadixPlan<256> { static constexpr int R1 = 16, R2 = 16, R3 = 1, R4 = 1; };
+template <> struct RadixPlan<512> { static constexpr int R1 = 8, R2 = 8, R3 = 8, R4 = 1; };
+template <> struct RadixPlan<1024> { static constexpr int R1 = 16, R2 = 16, R3 = 4, R4 = 1; };
+// lengths 3 * 2^a: the first radix carries the factor 3 (the later ones must divide it); 384 and
+// 768 take a fourth pass instead of a first radix of 24
+template <> struct RadixPlan<12> { static constexpr int R1 = 12, R2 = 1, R3 = 1, R4 = 1; };
+template <> struct RadixPlan<24> { static constexpr int R1 = 12, R2 = 2, R3 = 1, R4 = 1; };
+template <> struct RadixPlan<48> { static constexpr int R1 = 12, R2 = 4, R3 = 1, R4 = 1; };
+template <> struct RadixPlan<96> { static constexpr int R1 = 12, R2 = 4, R3 = 2, R4 = 1; };
+template <> struct RadixPlan<192> { static constexpr int R1 = 12, R2 = 4, R3 = 4, R4 = 1; };
+template <> struct RadixPlan<384> { static constexpr int R1 = 12, R2 = 4, R3 = 4, R4 = 2; };
+template <> struct RadixPlan<768> { static constexpr int R1 = 12, R2 = 4, R3 = 4, R4 = 4; };
 // Plan per element type and pass kind: FP64 256-point lines along the contiguous axis use
 // radix 8 x 8 x 4 (eight values per thread: half the registers of radix 16, one more LDS
 // exchange); measured slower for the strided passes, which keep radix 16 x 16.
 template <typename T, int N, bool CONTIG> struct Radix : RadixPlan<N> {};
-template <> struct Radix<double, 256, true> { static constexpr int R1 = 8, R2 = 8, R3 = 4; };
+template <> struct Radix<double, 256, true> { static constexpr int R1 = 8, R2 = 8, R3 = 4, R4 = 1; };
 
 // FP64 lines of up to 512 points exchange the real parts through LDS, then the imaginary
 // parts: half the LDS footprint of a line (twice the resident lines per CU) for the same
@@ -160,11 +125,11 @@ __device__ __forceinline__ void stockham_compute(int j0, int Ns, const C<T>* __r
     const int jm = (j0 + TL * b) % Ns;
 #pragma unroll
     for (int r = 1; r < R; ++r) {
-      C<T> w = tw[(r * jm * (N / (Ns * R))) & (N - 1)];
+      C<T> w = tw[r * jm * (N / (Ns * R))];      // r jm < Ns R: the index stays below N
       if (SIGN > 0) w.im = -w.im;
       v[b * R + r] = cmul(v[b * R + r], w);
     }
-    dft_regs<T, R, SIGN>(v + b * R);
+    dft_any<T, R, SIGN>(v + b * R);
   }
 }
 
@@ -172,7 +137,7 @@ __device__ __forceinline__ void stockham_compute(int j0, int Ns, const C<T>* __r
 // holds the outputs k = j + r*(N/Rlast), j = j0 + TL*b, in v[b*Rlast + r].
 template <typename T, int N, int SIGN, typename P, typename Addr>
 __device__ __forceinline__ void line_fft(LdsElem<T, N>* lds, Addr addr, int j0, const C<T>* __restrict__ tw, C<T>* v) {
-  dft_regs<T, P::R1, SIGN>(v);
+  dft_any<T, P::R1, SIGN>(v);
   if constexpr (P::R2 > 1) {
     stockham_exchange<T, N, P::R1, P::R1, P::R2>(lds, addr, j0, 1, v);
     stockham_compute<T, N, P::R1, P::R2, SIGN>(j0, P::R1, tw, v);
@@ -180,13 +145,18 @@ __device__ __forceinline__ void line_fft(LdsElem<T, N>* lds, Addr addr, int j0, 
       __syncthreads();
       stockham_exchange<T, N, P::R1, P::R2, P::R3>(lds, addr, j0, P::R1, v);
       stockham_compute<T, N, P::R1, P::R3, SIGN>(j0, P::R1 * P::R2, tw, v);
+      if constexpr (P::R4 > 1) {
+        __syncthreads();
+        stockham_exchange<T, N, P::R1, P::R3, P::R4>(lds, addr, j0, P::R1 * P::R2, v);
+        stockham_compute<T, N, P::R1, P::R4, SIGN>(j0, P::R1 * P::R2 * P::R3, tw, v);
+      }
     }
   }
 }
 
 template <typename P, int N>
 struct LineOut {
-  static constexpr int RL = P::R3 > 1 ? P::R3 : (P::R2 > 1 ? P::R2 : P::R1);
+  static constexpr int RL = P::R4 > 1 ? P::R4 : (P::R3 > 1 ? P::R3 : (P::R2 > 1 ? P::R2 : P::R1));
   static constexpr int TL = N / P::R1;
   // output index held in v[i] by thread j0
   __device__ static __forceinline__ int k(int j0, int i) {
@@ -281,8 +251,8 @@ __device__ __forceinline__ void line_to_natural(LdsElem<T, N>* lds, Addr addr, i
 // transforms, the symbol and the exchange fit in 128 VGPRs (four waves per SIMD; with sixteen
 // FP64 values per thread the kernel spills or runs one wave per SIMD).
 template <int N> struct SymbolRadix : RadixPlan<N> {};
-template <> struct SymbolRadix<128> { static constexpr int R1 = 8, R2 = 4, R3 = 4; };
-template <> struct SymbolRadix<256> { static constexpr int R1 = 8, R2 = 8, R3 = 4; };
+template <> struct SymbolRadix<128> { static constexpr int R1 = 8, R2 = 4, R3 = 4, R4 = 1; };
+template <> struct SymbolRadix<256> { static constexpr int R1 = 8, R2 = 8, R3 = 4, R4 = 1; };
 
 // Lines (., y, z) of the padded spectrum for y in [0, d1) and z in [0, nz); B consecutive z per
 // workgroup.  See launch_symbol.
@@ -357,7 +327,7 @@ __global__ void __launch_bounds__(MAXT, 1024 / MAXT) k_fft_symbol(C<T>* __restri
 // output complex line.  C2R_TRUNC: input complex line, output
 // Re(line[fmap(c2)]) times the deconvolution factors into phi[N0][N1][N2].
 template <typename T, int N, int SIGN, int MODE>
-__global__ void __launch_bounds__(256) k_fft_contig(const void* in, void* out,
+__global__ void __launch_bounds__(kContigThreads) k_fft_contig(const void* in, void* out,
                                                     int n0, int n1, int d0, int d1, int nc2, int z0, int nz,
                                                     const double* __restrict__ D0, const double* __restrict__ D1,
                                                     const double* __restrict__ D2,
@@ -398,7 +368,7 @@ __global__ void __launch_bounds__(256) k_fft_contig(const void* in, void* out,
 #pragma unroll
     for (int r = 0; r < P::R1; ++r) {
       const int k = j0 + r * TL;
-      v[r] = valid && ((k - z0) & (N - 1)) < nz ? F[lbase + k] : C<T>{0, 0};
+      v[r] = valid && (k - z0 + N) % N < nz ? F[lbase + k] : C<T>{0, 0};
     }
   }
   line_fft<T, N, SIGN, P>(my, addr, j0, tw, v);
@@ -425,7 +395,7 @@ __global__ void __launch_bounds__(256) k_fft_contig(const void* in, void* out,
 #pragma unroll
     for (int i = 0; i < P::R1; ++i) {
       const int k = LineOut<P, N>::k(j0, i);
-      if (((k - z0) & (N - 1)) < nz) F[lbase + k] = v[i];
+      if ((k - z0 + N) % N < nz) F[lbase + k] = v[i];
     }
   }
 }
@@ -439,9 +409,10 @@ static hipError_t launch_strided_n(C<T>* F, int axis, int d0, int d1, int d2, in
   // contiguous axis (coalescing) as far as 1024 threads and 64 KB of LDS allow; a window
   // of the last axis is covered in blocks of lines that divide its start and length
   int B = 256 / TL;
-  while (B * static_cast<int>(sizeof(C<T>)) < 128 && 2 * B * TL <= 1024 &&
+  while (B * static_cast<int>(sizeof(C<T>)) < kStridedSeg && 2 * B * TL <= kStridedThreads &&
          static_cast<size_t>(2 * B) * N * sizeof(LdsElem<T, N>) <= 65536)
     B *= 2;
+  while (B > 1 && static_cast<size_t>(B) * N * sizeof(LdsElem<T, N>) > 65536) B >>= 1;
   while (B > d2) B >>= 1;
   while (B > 1 && (z0 % B != 0 || nz % B != 0)) B >>= 1;
   if (z0 % B != 0 || nz % B != 0 || nz > d2 || z0 < 0 || z0 >= d2) return hipErrorInvalidValue;
@@ -472,6 +443,13 @@ hipError_t launch_strided(int n, C<T>* F, int axis, int d0, int d1, int d2, int 
     case 256: return launch_strided_n<T, 256, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, nc_out, z0, nz, tw, s);
     case 512: return launch_strided_n<T, 512, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, nc_out, z0, nz, tw, s);
     case 1024: return launch_strided_n<T, 1024, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, nc_out, z0, nz, tw, s);
+    case 12: return launch_strided_n<T, 12, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, nc_out, z0, nz, tw, s);
+    case 24: return launch_strided_n<T, 24, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, nc_out, z0, nz, tw, s);
+    case 48: return launch_strided_n<T, 48, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, nc_out, z0, nz, tw, s);
+    case 96: return launch_strided_n<T, 96, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, nc_out, z0, nz, tw, s);
+    case 192: return launch_strided_n<T, 192, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, nc_out, z0, nz, tw, s);
+    case 384: return launch_strided_n<T, 384, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, nc_out, z0, nz, tw, s);
+    case 768: return launch_strided_n<T, 768, SIGN>(F, axis, d0, d1, d2, n_o, o_compact, nc, in_c, out_c, nc_out, z0, nz, tw, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -480,10 +458,11 @@ template <typename T, int N>
 static hipError_t launch_symbol_n(C<T>* F, int d1, int d2, int nc, int nz, const SplitSymbol& sp, const C<T>* tw,
                                   hipStream_t s) {
   constexpr int TL = N / SymbolRadix<N>::R1;
-  int B = 256 / TL;   // as in the strided pass: >= 128-byte row segments where LDS allows
-  while (B * static_cast<int>(sizeof(C<T>)) < 128 && 2 * B * TL <= 1024 &&
+  int B = 256 / TL;   // as in the strided pass: >= kStridedSeg-byte row segments where LDS allows
+  while (B * static_cast<int>(sizeof(C<T>)) < kStridedSeg && 2 * B * TL <= kStridedThreads &&
          static_cast<size_t>(2 * B) * N * sizeof(LdsElem<T, N>) <= 65536)
     B *= 2;
+  while (B > 1 && static_cast<size_t>(B) * N * sizeof(LdsElem<T, N>) > 65536) B >>= 1;
   while (B > 1 && nz % B != 0) B >>= 1;
   if (nz <= 0 || 2 * nz > d2 || nz % B != 0 || nc > N || nc < 1) return hipErrorInvalidValue;
   const size_t shm = static_cast<size_t>(B) * N * sizeof(LdsElem<T, N>);
@@ -507,6 +486,13 @@ hipError_t launch_symbol(int n, C<T>* F, int d1, int d2, int nc, int nz, const S
     case 256: return launch_symbol_n<T, 256>(F, d1, d2, nc, nz, sp, tw, s);
     case 512: return launch_symbol_n<T, 512>(F, d1, d2, nc, nz, sp, tw, s);
     case 1024: return launch_symbol_n<T, 1024>(F, d1, d2, nc, nz, sp, tw, s);
+    case 12: return launch_symbol_n<T, 12>(F, d1, d2, nc, nz, sp, tw, s);
+    case 24: return launch_symbol_n<T, 24>(F, d1, d2, nc, nz, sp, tw, s);
+    case 48: return launch_symbol_n<T, 48>(F, d1, d2, nc, nz, sp, tw, s);
+    case 96: return launch_symbol_n<T, 96>(F, d1, d2, nc, nz, sp, tw, s);
+    case 192: return launch_symbol_n<T, 192>(F, d1, d2, nc, nz, sp, tw, s);
+    case 384: return launch_symbol_n<T, 384>(F, d1, d2, nc, nz, sp, tw, s);
+    case 768: return launch_symbol_n<T, 768>(F, d1, d2, nc, nz, sp, tw, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -518,7 +504,8 @@ static hipError_t launch_contig_n(const void* in, void* out, int n0, int n1, int
   if (z0 < 0 || z0 >= N || nz < 0 || nz > N) return hipErrorInvalidValue;
   constexpr int TL = N / Radix<T, N, true>::R1;
   constexpr int LS = N + N / Radix<T, N, true>::R1;
-  int B = 256 / TL;
+  int B = kContigThreads / TL;
+  if (B < 1) B = 1;
   while (B > 1 && static_cast<size_t>(B) * LS * sizeof(LdsElem<T, N>) > 65536) B >>= 1;
   const int nlines = n0 * n1;
   const size_t shm = static_cast<size_t>(B) * LS * sizeof(LdsElem<T, N>);
@@ -541,6 +528,13 @@ hipError_t launch_contig(int n, const void* in, void* out, int n0, int n1, int d
     case 256: return launch_contig_n<T, 256, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s);
     case 512: return launch_contig_n<T, 512, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s);
     case 1024: return launch_contig_n<T, 1024, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s);
+    case 12: return launch_contig_n<T, 12, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s);
+    case 24: return launch_contig_n<T, 24, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s);
+    case 48: return launch_contig_n<T, 48, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s);
+    case 96: return launch_contig_n<T, 96, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s);
+    case 192: return launch_contig_n<T, 192, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s);
+    case 384: return launch_contig_n<T, 384, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s);
+    case 768: return launch_contig_n<T, 768, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s);
     default: return hipErrorInvalidValue;
   }
 }

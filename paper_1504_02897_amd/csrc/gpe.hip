@@ -362,15 +362,15 @@ int gpe_reduction_blocks(const DevicePlan& P) {
 template <typename T, int SIGN>
 static hipError_t fft3_full(DevicePlan& P, C<T>* X, hipStream_t s, const C<T>* in = nullptr) {
   const HostTables& H = P.H;
-  const C<T>* tw2 = reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.N[2])]);
+  const C<T>* tw2 = reinterpret_cast<const C<T>*>(P.twiddles[tw_slot(H.N[2])]);
   const C<T>* src = in ? in : X;
   DDI_CHECK((launch_contig<T, SIGN, C2C>(H.N[2], src, X, H.N[0], H.N[1], H.N[0], H.N[1], H.N[2], 0, H.N[2], nullptr,
                                          nullptr, nullptr, tw2, s)));
   DDI_CHECK((launch_strided<T, SIGN>(H.N[1], X, 1, H.N[0], H.N[1], H.N[2], H.N[0], 0, H.N[1], 0, 0, H.N[1], 0, H.N[2],
-                                     reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.N[1])]), s)));
+                                     reinterpret_cast<const C<T>*>(P.twiddles[tw_slot(H.N[1])]), s)));
   if (H.N[0] > 1) {
     DDI_CHECK((launch_strided<T, SIGN>(H.N[0], X, 0, H.N[0], H.N[1], H.N[2], H.N[1], 0, H.N[0], 0, 0, H.N[0], 0, H.N[2],
-                                       reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.N[0])]), s)));
+                                       reinterpret_cast<const C<T>*>(P.twiddles[tw_slot(H.N[0])]), s)));
   }
   return hipSuccess;
 }

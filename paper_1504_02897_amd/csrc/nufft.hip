@@ -771,16 +771,16 @@ static hipError_t type2_fft(DevicePlan& P, int which, const T* rho, hipStream_t 
   const int ny = H.sched[which].ny;                               // and on axis 1 only its lines
   const int ycut = ny < H.nf[1];
   C<T>* F = reinterpret_cast<C<T>*>(P.fine);
-  const C<T>* tw2 = reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[2])]);
+  const C<T>* tw2 = reinterpret_cast<const C<T>*>(P.twiddles[tw_slot(H.nf[2])]);
   DDI_CHECK((launch_contig<T, SIGN, R2C_PAD>(H.nf[2], rho, F, H.N[0], H.N[1], H.nf[0], H.nf[1], H.N[2], z0, nz,
                                              P.deconv[0], P.deconv[1], P.deconv[2], tw2, s)));
   DDI_REC(1);
   DDI_CHECK((launch_strided<T, SIGN>(H.nf[1], F, 1, H.nf[0], H.nf[1], H.nf[2], H.N[0], 1, H.N[1], 1, ycut, ny, z0,
-                                     nz, reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[1])]), s)));
+                                     nz, reinterpret_cast<const C<T>*>(P.twiddles[tw_slot(H.nf[1])]), s)));
   DDI_REC(2);
   if (H.nf[0] > 1) {
     DDI_CHECK((launch_strided<T, SIGN>(H.nf[0], F, 0, H.nf[0], H.nf[1], H.nf[2], ny, ycut, H.N[0], 1, 0, H.N[0], z0,
-                                       nz, reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[0])]), s)));
+                                       nz, reinterpret_cast<const C<T>*>(P.twiddles[tw_slot(H.nf[0])]), s)));
   }
   DDI_REC(3);
   return hipSuccess;
@@ -796,13 +796,13 @@ static hipError_t type1_fft(DevicePlan& P, int which, T* phi, hipStream_t s, hip
   C<T>* F = reinterpret_cast<C<T>*>(P.fine);
   if (H.nf[0] > 1) {
     DDI_CHECK((launch_strided<T, SIGN>(H.nf[0], F, 0, H.nf[0], H.nf[1], H.nf[2], ny, ycut, H.N[0], 0, 1, H.N[0], z0,
-                                       nz, reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[0])]), s)));
+                                       nz, reinterpret_cast<const C<T>*>(P.twiddles[tw_slot(H.nf[0])]), s)));
   }
   DDI_REC(7);
   DDI_CHECK((launch_strided<T, SIGN>(H.nf[1], F, 1, H.nf[0], H.nf[1], H.nf[2], H.N[0], 1, ny, ycut, 1, H.N[1], z0,
-                                     nz, reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[1])]), s)));
+                                     nz, reinterpret_cast<const C<T>*>(P.twiddles[tw_slot(H.nf[1])]), s)));
   DDI_REC(8);
-  const C<T>* tw2 = reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[2])]);
+  const C<T>* tw2 = reinterpret_cast<const C<T>*>(P.twiddles[tw_slot(H.nf[2])]);
   DDI_CHECK((launch_contig<T, SIGN, C2R_TRUNC>(H.nf[2], F, phi, H.N[0], H.N[1], H.nf[0], H.nf[1], H.N[2], z0, nz,
                                                P.deconv[0], P.deconv[1], P.deconv[2], tw2, s)));
   DDI_REC(9);
@@ -990,8 +990,8 @@ hipError_t split_short_front(DevicePlan& P, const T* rho, hipStream_t s) {
   if (!H.split || !P.ones || !P.fine_short) return hipErrorInvalidValue;
   C<T>* F = reinterpret_cast<C<T>*>(P.fine_short);
   const int nz = H.N[2];
-  const C<T>* tw1 = reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[1])]);
-  const C<T>* tw2 = reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[2])]);
+  const C<T>* tw1 = reinterpret_cast<const C<T>*>(P.twiddles[tw_slot(H.nf[1])]);
+  const C<T>* tw2 = reinterpret_cast<const C<T>*>(P.twiddles[tw_slot(H.nf[2])]);
   SplitSymbol sp;
   for (int i = 0; i < 3; ++i) sp.dk[i] = 2.0 * M_PI / (H.nf[i] * H.h[i]);
   sp.inv_s2 = 1.0 / (H.split_s * H.split_s);
@@ -1018,7 +1018,7 @@ hipError_t split_short_front(DevicePlan& P, const T* rho, hipStream_t s) {
   DDI_CHECK((launch_contig<T, -1, R2C_PAD>(H.nf[2], rho, F, H.N[0], H.N[1], H.nf[0], H.nf[1], H.N[2], 0, nz, P.ones,
                                            P.ones, P.ones, tw2, s)));
   if (H.dim == 2) return launch_symbol<T>(H.nf[1], F, 1, H.nf[2], H.N[1], nz, sp, tw1, s);
-  const C<T>* tw0 = reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[0])]);
+  const C<T>* tw0 = reinterpret_cast<const C<T>*>(P.twiddles[tw_slot(H.nf[0])]);
   DDI_CHECK((launch_strided<T, -1>(H.nf[1], F, 1, H.nf[0], H.nf[1], H.nf[2], H.N[0], 1, H.N[1], 1, 0, H.N[1], 0, nz,
                                    tw1, s)));
   DDI_CHECK((launch_symbol<T>(H.nf[0], F, H.nf[1], H.nf[2], H.N[0], nz, sp, tw0, s)));
@@ -1031,7 +1031,7 @@ template <typename T>
 hipError_t split_short_back(DevicePlan& P, T* phi, hipStream_t s) {
   const HostTables& H = P.H;
   if (!H.split || !P.ones || !P.fine_short) return hipErrorInvalidValue;
-  const C<T>* tw2 = reinterpret_cast<const C<T>*>(P.twiddles[ilog2(H.nf[2])]);
+  const C<T>* tw2 = reinterpret_cast<const C<T>*>(P.twiddles[tw_slot(H.nf[2])]);
   return launch_contig<T, 1, C2R_ADD>(H.nf[2], P.fine_short, phi, H.N[0], H.N[1], H.nf[0], H.nf[1], H.N[2], 0,
                                       H.N[2], P.ones, P.ones, P.ones, tw2, s);
 }

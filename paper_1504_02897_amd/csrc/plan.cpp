@@ -15,6 +15,8 @@ namespace {
 constexpr long double kPiL = 3.141592653589793238462643383279502884L;
 
 bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+// grid sizes the FFT passes take: 2^a, or 3 * 2^a (radix 3 in the first pass)
+bool fft_size(int64_t v) { return is_pow2(v) || (v % 3 == 0 && is_pow2(v / 3)); }
 
 // n-point Gauss-Legendre rule on [-1, 1]: Newton's method on P_n evaluated by
 // the three-term recurrence, carried in long double.
@@ -337,7 +339,7 @@ std::string build_tables(const ddi_params& p, HostTables& t, int* status) {
   if (p.dim != 2 && p.dim != 3) return "dim must be 2 or 3";
   const int d = p.dim;
   for (int a = 0; a < d; ++a) {
-    if (!is_pow2(p.n[a])) return "grid sizes must be powers of two";
+    if (!fft_size(p.n[a])) return "grid sizes must be powers of two or three times a power of two";
     if (!(p.L[a] > 0.0) || !std::isfinite(p.L[a])) return "L must be positive and finite";
   }
   double nn = std::sqrt(p.dip_n[0] * p.dip_n[0] + p.dip_n[1] * p.dip_n[1] + p.dip_n[2] * p.dip_n[2]);
@@ -384,7 +386,11 @@ std::string build_tables(const ddi_params& p, HostTables& t, int* status) {
     t.ib[a] = t.N[a] == 1 ? 1 : (d == 3 ? kInterpBlock3 : 8);
     t.ireg[a] = t.ib[a] + t.W[a] - 1;
   }
-  for (int a = 0; a < 3; ++a) t.ntiles[a] = t.nf[a] / t.tile[a];
+  for (int a = 0; a < 3; ++a) {
+    if (t.nf[a] % t.tile[a] != 0)   // (only for 3 * 2^a: the fine grid of a 2D axis below 96 points)
+      return "the oversampled grid must be a multiple of the spread tile (64 on the first axis of a 2D grid)";
+    t.ntiles[a] = t.nf[a] / t.tile[a];
+  }
 
   // ---------------------------------------------------------------- quadrature
   double hp[3] = {0, 0, 0};      // h in paper axes

@@ -96,7 +96,7 @@ int main(int argc, char** argv) {
       put_i(pre + "nslots_z0_nz_ny", win, 4);
     }
   }
-  for (int n : {4, 64, 256, 1024}) put_d("twiddle" + std::to_string(n), ddi::twiddle_table(n));
+  for (int n : {4, 64, 256, 1024, 12, 96, 192, 768}) put_d("twiddle" + std::to_string(n), ddi::twiddle_table(n));
   std::fclose(out);
   return 0;
 }

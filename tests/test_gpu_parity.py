@@ -551,3 +551,97 @@ def test_ts_step_loss_mixed_matches_oracle():
     err = relinf(out.cpu().numpy().astype(np.complex128), ref)
     say(f"  rel Linf = {err:.3e}")
     assert err < MIXED_TOL
+
+
+# ---------------------------------------------------------------- grid sizes 3 * 2^a (radix 3)
+@pytest.mark.parametrize("n,L,quad", [((96, 96, 96), (12.0,) * 3, (24, 12, 24)),
+                                      ((24, 48, 96), (6.0, 8.0, 12.0), (16, 8, 16)),
+                                      ((12, 12, 12), (3.0,) * 3, (8, 4, 8))],
+                         ids=["96^3", "24x48x96", "12^3"])
+def test_radix3_grids_fp64(n, L, quad):
+    """Grids of 3 * 2^a points (the paper's 96^3 of Table 7): fine axes of 24 to 192 points, whose
+    FFT passes carry a radix-3 stage.  Apply, type-2 and type-1 against the oracle (FP64 bar)."""
+    say(f"case: radix-3 grid {n} fp64")
+    plan, prob = make(3, n, L, quad, dip_n=(0.6, 0.0, 0.8), tol=1e-13 if n[0] >= 24 else 1e-7)
+    bound = FP64_TOL if n[0] >= 24 else 1e-6
+    assert plan.info["n_fine"] == tuple(2 * v for v in n)
+    lumps, _ = I.mixture_lumps(6, 3, (2, 3), centre=1.0, widths=(0.8, 1.5))
+    psi, _ = I.normalise(I.lumps_on_grid(lumps, n, L), n, L)
+    rho = np.abs(psi) ** 2
+    phi = plan.apply(to_dev(rho, torch.float64)).cpu().numpy()
+    err = relinf(phi, O.ddi_apply(rho, prob))
+    say(f"  apply rel Linf = {err:.3e}")
+    assert err < bound
+    rows, quad_o, _ = oracle_rows(plan, prob)
+    rh = plan.type2(to_dev(rho, torch.float64)).cpu().numpy()
+    ref2 = O.rhohat(rho, prob, quad_o.k[rows])
+    err2 = float(np.max(np.abs(rh - ref2)) / np.max(np.abs(ref2)))
+    say(f"  type2 rel Linf = {err2:.3e}")
+    assert err2 < bound
+    rng = np.random.default_rng(9)
+    g = rng.standard_normal(plan.m_eff) + 1j * rng.standard_normal(plan.m_eff)
+    err1 = relinf(plan.type1(to_dev(g, torch.complex128)).cpu().numpy(), O.nodes_to_grid(g, prob, quad_o.k[rows]))
+    say(f"  type1 rel Linf = {err1:.3e}")
+    assert err1 < bound
+    # the GPE's unpadded FFTs (lengths 12 to 96) through the energy and gradient
+    gp = O.GPEParams(beta=30.0, lam=20.0, gamma=(1.0, 1.0, 2.0))
+    E, G = plan.energy_grad(to_dev(psi, torch.complex128), gp.beta, gp.lam, gp.gamma)
+    E_or, G_or = O.gpe_energy_grad(psi, prob, gp)
+    say(f"  energies rel {np.max(np.abs(E - E_or)) / np.max(np.abs(E_or)):.3e}, gradient {relinf(G.cpu().numpy(), G_or):.3e}")
+    assert np.max(np.abs(E - E_or)) < bound * np.max(np.abs(E_or))
+    assert relinf(G.cpu().numpy(), G_or) < bound
+
+
+def test_radix3_long_lines():
+    """Transforms of 384 and 768 points (four Stockham passes 12 x 4 x 4 x 2 and 12 x 4 x 4 x 4):
+    a 16 x 16 x 192 grid (fine last axis 384) against the oracle, and the GPE's unpadded 384-point
+    lines (8 x 8 x 384, lambda = 0) against the oracle's energy and gradient."""
+    say("case: radix-3 16x16x192 fp64 (384-point fine lines)")
+    n, L = (16, 16, 192), (4.0, 4.0, 24.0)
+    plan, prob = make(3, n, L, (12, 8, 16), dip_n=(0.6, 0.0, 0.8))
+    assert plan.info["n_fine"][2] == 384
+    rho = I.random_field(6, n) ** 2
+    err = relinf(plan.apply(to_dev(rho, torch.float64)).cpu().numpy(), O.ddi_apply(rho, prob))
+    say(f"  apply rel Linf = {err:.3e}")
+    assert err < FP64_TOL
+    say("case: radix-3 8x8x384 GPE (384-point grid lines, 768-point fine lines)")
+    n, L = (8, 8, 384), (2.0, 2.0, 24.0)
+    plan, prob = make(3, n, L, (4, 2, 4), dip_n=(0.6, 0.0, 0.8), kernel_width=4)
+    psi = I.random_field(7, n, complex_=True) * np.exp(-np.meshgrid(*I.grid_axes(n, L), indexing="ij")[2] ** 2 / 50)
+    psi, _ = I.normalise(psi, n, L)
+    gp = O.GPEParams(beta=10.0, lam=0.0, gamma=(1.0, 1.0, 0.3))
+    E, G = plan.energy_grad(to_dev(psi, torch.complex128), gp.beta, gp.lam, gp.gamma)
+    E_or, G_or = O.gpe_energy_grad(psi, prob, gp)
+    say(f"  energies {np.max(np.abs(E - E_or)):.3e}, gradient rel Linf {relinf(G.cpu().numpy(), G_or):.3e}")
+    assert np.max(np.abs(E - E_or)) < 1e-12 * np.max(np.abs(E_or))
+    assert relinf(G.cpu().numpy(), G_or) < FP64_TOL
+
+
+def test_radix3_mixed_2d_and_split():
+    """3 * 2^a in mixed precision (48^3), in 2D (96 x 192) and with the split of Eq. 3.9 (48^3, 96^2)."""
+    say("case: radix-3 48^3 mixed")
+    n, L = (48, 48, 48), (8.0,) * 3
+    plan, prob = make(3, n, L, (24, 12, 24), dip_n=(0.3, 0.4, math.sqrt(0.75)), prec="mixed")
+    lumps, _ = I.mixture_lumps(5, 3, (1, 4))
+    psi, _ = I.normalise(I.lumps_on_grid(lumps, n, L), n, L)
+    rho32 = (np.abs(psi) ** 2).astype(np.float32)
+    phi = plan.apply(to_dev(rho32, torch.float32)).cpu().numpy().astype(np.float64)
+    err = relinf(phi, O.ddi_apply(rho32.astype(np.float64), prob))
+    say(f"  mixed rel Linf = {err:.3e}")
+    assert err < MIXED_TOL
+    say("case: radix-3 2D 96x192 fp64")
+    n2, L2 = (96, 192), (8.0, 16.0)
+    plan, prob = make(2, n2, L2, (32, 1, 64), dip_n=(math.sqrt(0.5), 0.0, math.sqrt(0.5)))
+    rho2 = I.random_field(4, n2) ** 2
+    err = relinf(plan.apply(to_dev(rho2, torch.float64)).cpu().numpy(), O.ddi_apply(rho2, prob))
+    say(f"  2D rel Linf = {err:.3e}")
+    assert err < FP64_TOL
+    for dim, ns, Ls, q in ((3, (48, 48, 48), (8.0,) * 3, (16, 16, 32)), (2, (96, 96), (8.0, 8.0), (24, 1, 48))):
+        say(f"case: radix-3 split {ns}")
+        s_, r2 = O.split_defaults(Ls, 1e-13)
+        sp = DDIPlan(dim, ns, Ls, dip_n=(0.6, 0.0, 0.8), quad=q, tol=1e-13, split=True)
+        pr = O.DDIProblem(dim=dim, n=ns, L=Ls, dip_n=(0.6, 0.0, 0.8), n_rad=q[0], n_pol=q[1], n_azi=q[2], kmax=r2)
+        r = I.random_field(5, ns) ** 2
+        err = relinf(sp.apply(to_dev(r, torch.float64)).cpu().numpy(), O.split_apply(r, pr, s_))
+        say(f"  split rel Linf = {err:.3e}")
+        assert err < FP64_TOL

@@ -81,6 +81,13 @@ CASES = {
     # a small ball whose supports end on the last position of a tile: the axis-1 window is tight
     "3d_split_64": (dict(dim=3, n=(64, 64, 64), L=(8.0,) * 3, quad=(12, 12, 24), tol=1e-13, split=True, split_s=1.5),
                     dict(dim=3, n=(64, 64, 64), L=(8.0,) * 3, n_rad=12, n_pol=12, n_azi=24)),
+    # grid sizes 3 * 2^a (radix 3 in the FFT passes): fine axes 192, 96, 48
+    "3d_radix3": (dict(dim=3, n=(96, 48, 24), L=(12.0, 8.0, 6.0), dip_n=(0.6, 0.0, 0.8), quad=(24, 12, 24), tol=1e-13),
+                  dict(dim=3, n=(96, 48, 24), L=(12.0, 8.0, 6.0), dip_n=(0.6, 0.0, 0.8), n_rad=24, n_pol=12, n_azi=24)),
+    "2d_radix3": (dict(dim=2, n=(96, 192), L=(8.0, 16.0), dip_n=(0.7071067811865476, 0.0, 0.7071067811865476),
+                       quad=(32, 1, 64), tol=1e-13),
+                  dict(dim=2, n=(96, 192), L=(8.0, 16.0), dip_n=(0.7071067811865476, 0.0, 0.7071067811865476),
+                       n_rad=32, n_pol=1, n_azi=64)),
     # the 2D split: I_2 weights times erfc(|k|/s) on the small polar ball
     "2d_split": (dict(dim=2, n=(128, 128), L=(16.0, 16.0), dip_n=(0.0, -0.896, 0.44404),
                       dip_m=(0.0, -0.52476, 0.85125), quad=(32, 1, 64), tol=1e-13, split=True),
@@ -294,7 +301,7 @@ def test_twiddle_tables_are_the_roots_of_unity(tables):
     mp = pytest.importorskip("mpmath")
     mp.mp.dps = 40
     t = tables["3d_fp64"]
-    for n in (4, 64, 256, 1024):
+    for n in (4, 64, 256, 1024, 12, 96, 192, 768):
         tw = t[f"twiddle{n}"]
         assert tw.size == 2 * n
         ang = [2 * mp.pi * k / n for k in range(n)]
@@ -306,6 +313,25 @@ def test_twiddle_tables_are_the_roots_of_unity(tables):
 
 
 def test_rejected_parameters_report_an_error(driver, tmp_path):
-    t = run_tables(driver, tmp_path, dim=3, n=(48, 32, 32), L=(8.0,) * 3)
+    t = run_tables(driver, tmp_path, dim=3, n=(40, 32, 32), L=(8.0,) * 3)
     assert int(t["status"][0]) != 0
     assert "power" in t["message"]
+    # 3 * 2^a is taken, but a 2D first axis below 96 points does not fill whole 64-point tiles
+    t = run_tables(driver, tmp_path, dim=2, n=(48, 64), L=(8.0, 8.0))
+    assert int(t["status"][0]) != 0 and "tile" in t["message"]
+
+
+def test_in_register_dfts_match_the_direct_sum(tmp_path):
+    """The in-register DFTs of the FFT passes (csrc/fft_regs.h), every radix the plans use
+    (2, 4, 8, 16 and the radix-3 forms 12 and 24), both signs, against the direct sum in long
+    double (tests/host/fft_regs_check.cpp, built with g++)."""
+    gxx = shutil.which("g++")
+    if gxx is None or not os.path.isdir(ROCM_INC):
+        pytest.skip("g++ or the ROCm headers are not available")
+    exe = str(tmp_path / "fft_regs_check")
+    src = os.path.join(ROOT, "tests", "host", "fft_regs_check.cpp")
+    r = subprocess.run([gxx, "-std=c++17", "-O2", "-D__HIP_PLATFORM_AMD__", "-I" + ROCM_INC, src, "-o", exe],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([exe], capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout + r.stderr
