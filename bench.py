@@ -280,12 +280,22 @@ def gf_timed_flow(p, psi0, wl, torch, I):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     step_ms = time_steps(lambda: p.gf_step(a, beta, lam, gam, dt=dt, out=b), 20, 2, torch)
+    # the host's own cost of a step: 20 steps enqueued with no synchronisation in between (the
+    # launches return before the kernels run); above the GPU time per step, the host paces the flow
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(20):
+        p.gf_step(a, beta, lam, gam, dt=dt, out=b)
+    host_ms = 1000.0 * (time.perf_counter() - t0) / 20
+    torch.cuda.synchronize()
     return psi, hist, {"steps": wl["steps"], "ms_per_step": round(step_ms, 4),
                        "flow_ms_per_step": round(1000.0 * el / wl["steps"], 4),
+                       "host_enqueue_ms_per_step": round(host_ms, 4),
                        "energy_reports": len(hist),
                        "timing": "ms_per_step: 20 back-to-back gpe_gf_step calls between HIP events on the "
                                  "library's stream, after warm-up; flow_ms_per_step: wall clock of the 200-step "
-                                 f"flow including an energy report (synchronising) every {GF_ENERGY_EVERY} steps"}
+                                 f"flow including an energy report (synchronising) every {GF_ENERGY_EVERY} steps; "
+                                 "host_enqueue_ms_per_step: the host's time to enqueue one step, all of its launches"}
 
 
 def gf_twin_err(prec, torch, np, I, DDIPlan):

@@ -37,6 +37,11 @@ constexpr int kSpreadBatch = DDI_SPREAD_BATCH;
 // spread: a tile with more nodes is split into chunks of this many (partial tiles + reduce);
 // the matrix-core kernels take longer chunks (cheaper per node)
 constexpr int kSpreadChunk = DDI_SPREAD_CHUNK;
+#ifndef DDI_SPREAD_CHUNK_2D
+#define DDI_SPREAD_CHUNK_2D 32
+#endif
+// shortest chunk of the 2D spread (hot tiles are split into chunks of at least this many nodes)
+constexpr int kSpreadChunk2d = DDI_SPREAD_CHUNK_2D;
 constexpr int kSpreadChunkMfma = DDI_SPREAD_CHUNK_MFMA;
 #ifndef DDI_SPREAD_WAVES
 #define DDI_SPREAD_WAVES 4096

@@ -293,6 +293,96 @@ __global__ void __launch_bounds__(64) k_spread(C<T>* __restrict__ F, C<T>* __res
   }
 }
 
+// 2D spread: a work item is a tile of 64 positions on axis 1 by kTileZ on the last axis, one wave
+// per item, lane y owning the kTileZ points of its position in registers.  The item's nodes are
+// staged kSpreadBatch at a time in LDS, each as its axis-1 weight row (kWMax values, read whole),
+// the offset of the tile's first axis-1 position in its support, its kTileZ last-axis weights at
+// the tile's positions and its value; a lane looks its own axis-1 weight up in the row.  FP32
+// accumulates with Kahan compensation.
+template <typename T, bool KAHAN>
+__global__ void __launch_bounds__(64) k_spread2d(C<T>* __restrict__ F, C<T>* __restrict__ partial,
+                                                 const NodeRec<T>* __restrict__ nodes, const C<T>* __restrict__ g,
+                                                 const int32_t* __restrict__ list,
+                                                 const SpreadItem* __restrict__ items, int nf1, int nf2, int nt2,
+                                                 int w1, int w2) {
+  constexpr int TY = 64, TZ = kTileZ, NB = kSpreadBatch;
+  __shared__ T srow[NB][kWMax];
+  __shared__ T sz[NB][TZ];
+  __shared__ C<T> sg[NB];
+  __shared__ int soff[NB];
+  const int lane = threadIdx.x;
+  const SpreadItem it = items[blockIdx.x];
+  if (it.tile < 0) return;                   // padding item
+  const int tz = it.tile % nt2;
+  const int ty = it.tile / nt2;              // the unit axis 0 has one tile
+  const int y0 = ty * TY, z0 = tz * TZ;
+  C<T> acc[TZ], cmp[TZ];
+#pragma unroll
+  for (int i = 0; i < TZ; ++i) {
+    acc[i] = C<T>{0, 0};
+    cmp[i] = C<T>{0, 0};
+  }
+  for (int base = 0; base < it.count; base += NB) {
+    const int n = it.count - base < NB ? it.count - base : NB;
+    if (lane < n) {
+      const int q = list[it.start + base + lane];
+      const NodeRec<T>* nd = nodes + q;
+      int oy = y0 - nd->l0[1];               // support index of the tile's first axis-1 position
+      if (oy < 0) oy += nf1;
+      int dz = z0 - nd->l0[2];
+      if (dz < 0) dz += nf2;
+      soff[lane] = oy;
+#pragma unroll
+      for (int i = 0; i < kWMax; ++i) srow[lane][i] = nd->w[1][i];
+#pragma unroll
+      for (int i = 0; i < TZ; ++i) {
+        int d = dz + i;
+        if (d >= nf2) d -= nf2;
+        const T v = nd->w[2][d < kWMax ? d : kWMax - 1];
+        sz[lane][i] = d < w2 ? v : T(0);
+      }
+      sg[lane] = g[q];
+    }
+    __syncthreads();
+#pragma unroll DDI_SPREAD_UNROLL
+    for (int e = 0; e < n; ++e) {
+      int d = soff[e] + lane;                // this lane's support index on axis 1
+      if (d >= nf1) d -= nf1;
+      const T wr = srow[e][d < w1 ? d : 0];
+      const T wy = d < w1 ? wr : T(0);
+      const C<T> gq = sg[e];
+      const C<T> p = {gq.re * wy, gq.im * wy};
+#pragma unroll
+      for (int i = 0; i < TZ; ++i) {
+        const T wz = sz[e][i];
+        if (KAHAN) {
+          T yr = p.re * wz - cmp[i].re;
+          T tr = acc[i].re + yr;
+          cmp[i].re = (tr - acc[i].re) - yr;
+          acc[i].re = tr;
+          T yi = p.im * wz - cmp[i].im;
+          T ti = acc[i].im + yi;
+          cmp[i].im = (ti - acc[i].im) - yi;
+          acc[i].im = ti;
+        } else {
+          acc[i].re += p.re * wz;
+          acc[i].im += p.im * wz;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (it.slot < 0) {
+    C<T>* row = F + static_cast<int64_t>(y0 + lane) * nf2 + z0;
+#pragma unroll
+    for (int i = 0; i < TZ; ++i) row[i] = acc[i];
+  } else {
+    C<T>* pt = partial + static_cast<int64_t>(it.slot) * 64 * TZ;
+#pragma unroll
+    for (int i = 0; i < TZ; ++i) pt[i * 64 + lane] = acc[i];
+  }
+}
+
 // Cooperative weight loads of the matrix-core kernels.  For a block of 16 (tile, node)
 // entries, lane (g, t) = (lane / 8, lane % 8) takes the entries 2 g and 2 g + 1 (one 16-byte
 // load of their two records) and, for load j (0..5), the window of entry 2 g + j / 3 on axis
@@ -919,6 +1009,14 @@ static hipError_t spread_t(DevicePlan& P, int which, const C<T>* g, hipStream_t 
       hipLaunchKernelGGL((k_spread_mfma<T>), dim3(nitems), dim3(64), 0, s, F, reinterpret_cast<C<T>*>(P.partial),
                          reinterpret_cast<const T*>(P.pads), g, reinterpret_cast<const int2*>(D.ent), D.items, H.nf[1],
                          H.nf[2], H.ntiles[1], H.ntiles[2], ent_bytes(S), rows_bytes<T>(H), zero_record<T>(H));
+      done = true;
+    }
+  }
+  if constexpr (TX == 1) {
+    if (!done) {
+      hipLaunchKernelGGL((k_spread2d<T, kahan>), dim3(nitems), dim3(64), 0, s, F, reinterpret_cast<C<T>*>(P.partial),
+                         reinterpret_cast<const NodeRec<T>*>(P.nodes), g, D.list, D.items, H.nf[1], H.nf[2],
+                         H.ntiles[2], H.W[1], H.W[2]);
       done = true;
     }
   }

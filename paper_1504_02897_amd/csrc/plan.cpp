@@ -249,9 +249,13 @@ std::string build_spread_schedule(const HostTables& t, const std::vector<int64_t
   // would otherwise fill fewer items than the 4096 waves the spread keeps resident (a small
   // ball of nodes crowds a few tiles, and one wave per long chunk then sets the duration)
   int chunk = kSpreadChunk;
+  const int64_t per_wave = (count[ntile_total] + kSpreadWaves - 1) / kSpreadWaves;
   if (t.row_windows && kSpreadMfma) {
-    const int64_t per_wave = (count[ntile_total] + kSpreadWaves - 1) / kSpreadWaves;
     chunk = static_cast<int>(std::min<int64_t>(kSpreadChunkMfma, std::max<int64_t>(32, (per_wave + 15) / 16 * 16)));
+  } else if (t.dim == 2) {
+    // 2D: a few thousand tiles hold all the entries, one wave each, so the hot tiles (many nodes near
+    // k = 0) set the duration; chunks of about entries / resident waves (at least kSpreadChunk2d)
+    chunk = static_cast<int>(std::min<int64_t>(kSpreadChunk, std::max<int64_t>(kSpreadChunk2d, per_wave)));
   }
   S.items.clear();
   S.reduces.clear();
