@@ -37,6 +37,9 @@ constexpr int kSpreadBatch = DDI_SPREAD_BATCH;
 // spread: a tile with more nodes is split into chunks of this many (partial tiles + reduce);
 // the matrix-core kernels take longer chunks (cheaper per node)
 constexpr int kSpreadChunk = DDI_SPREAD_CHUNK;
+#ifndef DDI_INTERP_BREG
+#define DDI_INTERP_BREG 1      // the interpolation's tile fragments held in registers across blocks
+#endif
 #ifndef DDI_SPREAD_CHUNK_2D
 #define DDI_SPREAD_CHUNK_2D 32
 #endif

@@ -31,6 +31,18 @@ namespace ddi {
 constexpr int kStridedSeg = DDI_STRIDED_SEG;
 constexpr int kStridedThreads = DDI_STRIDED_THREADS;
 constexpr int kContigThreads = DDI_CONTIG_THREADS;
+#ifndef DDI_CONTIG_BLOCKS
+#define DDI_CONTIG_BLOCKS -1
+#endif
+#ifndef DDI_CONTIG_WAVESYNC
+#define DDI_CONTIG_WAVESYNC 1
+#endif
+// Workgroups of a contiguous pass: each loops over line groups with the next group's loads in
+// flight during this group's transform and stores.  -1: a quarter as many as there are line
+// groups, at least 512 (or all of them) and at most 1024; 0: one per line group; n > 0: n.
+// Wave-local LDS barriers where a line lies inside one wave.
+constexpr int kContigBlocks = DDI_CONTIG_BLOCKS;
+constexpr bool kContigWaveSync = DDI_CONTIG_WAVESYNC != 0;
 
 // ------------------------------------------------------------------ radix plans
 template <int N> struct RadixPlan;
@@ -67,10 +79,24 @@ struct SplitExchange {
 template <typename T, int N>
 using LdsElem = typename std::conditional<SplitExchange<T, N>::value, T, C<T>>::type;
 
+// Barrier between the LDS writes and reads of an exchange: the whole workgroup, or (WAVE) only
+// the wave, when every line lies inside one wave (LDS operations of a wave complete in order;
+// the fences keep the compiler from moving them across the barrier).
+template <bool WAVE>
+__device__ __forceinline__ void lds_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 // One LDS exchange between radix passes: the thread's R1 values (grouped for radix Rs,
 // written with stride Ns) are stored, then regathered for radix Rl.  On exit v holds the
 // raw (untwiddled) inputs of the next pass.
-template <typename T, int N, int R1, int Rs, int Rl, typename Addr>
+template <typename T, int N, int R1, int Rs, int Rl, bool WAVE = false, typename Addr>
 __device__ __forceinline__ void stockham_exchange(LdsElem<T, N>* lds, Addr addr, int j0, int Ns, C<T>* v) {
   constexpr int TL = N / R1;
   if constexpr (SplitExchange<T, N>::value) {
@@ -84,7 +110,7 @@ __device__ __forceinline__ void stockham_exchange(LdsElem<T, N>* lds, Addr addr,
 #pragma unroll
         for (int r = 0; r < Rs; ++r) lds[addr(idxD + r * Ns)] = part == 0 ? v[b * Rs + r].re : v[b * Rs + r].im;
       }
-      __syncthreads();
+      lds_sync<WAVE>();
 #pragma unroll
       for (int b = 0; b < R1 / Rl; ++b) {
         const int j = j0 + TL * b;
@@ -95,7 +121,7 @@ __device__ __forceinline__ void stockham_exchange(LdsElem<T, N>* lds, Addr addr,
           else v[b * Rl + r] = C<T>{keep[b * Rl + r], x};
         }
       }
-      if (part == 0) __syncthreads();
+      if (part == 0) lds_sync<WAVE>();
     }
   } else {
 #pragma unroll
@@ -105,7 +131,7 @@ __device__ __forceinline__ void stockham_exchange(LdsElem<T, N>* lds, Addr addr,
 #pragma unroll
       for (int r = 0; r < Rs; ++r) lds[addr(idxD + r * Ns)] = v[b * Rs + r];
     }
-    __syncthreads();
+    lds_sync<WAVE>();
 #pragma unroll
     for (int b = 0; b < R1 / Rl; ++b) {
       const int j = j0 + TL * b;
@@ -135,19 +161,19 @@ __device__ __forceinline__ void stockham_compute(int j0, int Ns, const C<T>* __r
 
 // Full line FFT.  On entry v[r] = x[j0 + r*TL] (r < R1).  On exit the thread
 // holds the outputs k = j + r*(N/Rlast), j = j0 + TL*b, in v[b*Rlast + r].
-template <typename T, int N, int SIGN, typename P, typename Addr>
+template <typename T, int N, int SIGN, typename P, bool WAVE = false, typename Addr>
 __device__ __forceinline__ void line_fft(LdsElem<T, N>* lds, Addr addr, int j0, const C<T>* __restrict__ tw, C<T>* v) {
   dft_any<T, P::R1, SIGN>(v);
   if constexpr (P::R2 > 1) {
-    stockham_exchange<T, N, P::R1, P::R1, P::R2>(lds, addr, j0, 1, v);
+    stockham_exchange<T, N, P::R1, P::R1, P::R2, WAVE>(lds, addr, j0, 1, v);
     stockham_compute<T, N, P::R1, P::R2, SIGN>(j0, P::R1, tw, v);
     if constexpr (P::R3 > 1) {
-      __syncthreads();
-      stockham_exchange<T, N, P::R1, P::R2, P::R3>(lds, addr, j0, P::R1, v);
+      lds_sync<WAVE>();
+      stockham_exchange<T, N, P::R1, P::R2, P::R3, WAVE>(lds, addr, j0, P::R1, v);
       stockham_compute<T, N, P::R1, P::R3, SIGN>(j0, P::R1 * P::R2, tw, v);
       if constexpr (P::R4 > 1) {
-        __syncthreads();
-        stockham_exchange<T, N, P::R1, P::R3, P::R4>(lds, addr, j0, P::R1 * P::R2, v);
+        lds_sync<WAVE>();
+        stockham_exchange<T, N, P::R1, P::R3, P::R4, WAVE>(lds, addr, j0, P::R1 * P::R2, v);
         stockham_compute<T, N, P::R1, P::R4, SIGN>(j0, P::R1 * P::R2 * P::R3, tw, v);
       }
     }
@@ -336,67 +362,92 @@ __global__ void __launch_bounds__(kContigThreads) k_fft_contig(const void* in, v
   LdsElem<T, N>* lds = reinterpret_cast<LdsElem<T, N>*>(smem_raw);
   using P = Radix<T, N, true>;
   constexpr int TL = N / P::R1;
+  constexpr bool kWave = kContigWaveSync && 64 % TL == 0;   // every line inside one wave
   constexpr int LS = N + N / P::R1;      // padded line stride in LDS
   const int j0 = threadIdx.x % TL;
   const int lb = threadIdx.x / TL;
-  const int line = blockIdx.x * B + lb;
-  const bool valid = line < nlines;
-  const int o0 = valid ? line / n1 : 0;
-  const int o1 = valid ? line % n1 : 0;
+  const int ngroups = (nlines + B - 1) / B;
   LdsElem<T, N>* my = lds + lb * LS;
   auto addr = [](int k) { return k + k / Radix<T, N, true>::R1; };
+  // the thread's inputs of line group g (zeros outside the line's active or windowed positions)
+  auto load = [&](int g, C<T>* v) {
+    const int line = g * B + lb;
+    const bool valid = line < nlines;
+    const int o0 = valid ? line / n1 : 0;
+    const int o1 = valid ? line % n1 : 0;
+    if (MODE == R2C_PAD) {
+      const T* rho = reinterpret_cast<const T*>(in);
+      const double s01 = D0[o0] * D1[o1];
+      const int64_t rb = (static_cast<int64_t>(o0) * n1 + o1) * nc2;
+#pragma unroll
+      for (int r = 0; r < P::R1; ++r) {
+        const int k = j0 + r * TL;
+        if (valid && active(k, N, nc2)) {
+          const int c2 = cmap(k, N, nc2);
+          v[r] = C<T>{static_cast<T>(static_cast<double>(rho[rb + c2]) * s01 * D2[c2]), T(0)};
+        } else {
+          v[r] = C<T>{0, 0};
+        }
+      }
+    } else {
+      const C<T>* F = reinterpret_cast<const C<T>*>(in);
+      int64_t lbase;
+      if (MODE == C2C) lbase = static_cast<int64_t>(line) * N;
+      else lbase = (static_cast<int64_t>(fmap(o0, d0, n0)) * d1 + fmap(o1, d1, n1)) * N;
+#pragma unroll
+      for (int r = 0; r < P::R1; ++r) {
+        const int k = j0 + r * TL;
+        v[r] = valid && (k - z0 + N) % N < nz ? F[lbase + k] : C<T>{0, 0};
+      }
+    }
+  };
+  auto store = [&](int g, const C<T>* v) {
+    const int line = g * B + lb;
+    if (line >= nlines) return;
+    const int o0 = line / n1;
+    const int o1 = line % n1;
+    if (MODE == C2R_TRUNC || MODE == C2R_ADD) {
+      T* phi = reinterpret_cast<T*>(out);
+      const double s01 = D0[o0] * D1[o1];
+      const int64_t rb = (static_cast<int64_t>(o0) * n1 + o1) * nc2;
+#pragma unroll
+      for (int i = 0; i < P::R1; ++i) {
+        const int k = LineOut<P, N>::k(j0, i);
+        if (active(k, N, nc2)) {
+          const int c2 = cmap(k, N, nc2);
+          const T val = static_cast<T>(static_cast<double>(v[i].re) * s01 * D2[c2]);
+          if (MODE == C2R_ADD) phi[rb + c2] += val;
+          else phi[rb + c2] = val;
+        }
+      }
+    } else {
+      C<T>* F = reinterpret_cast<C<T>*>(out);
+      int64_t lbase;
+      if (MODE == C2C) lbase = static_cast<int64_t>(line) * N;
+      else lbase = (static_cast<int64_t>(fmap(o0, d0, n0)) * d1 + fmap(o1, d1, n1)) * N;
+#pragma unroll
+      for (int i = 0; i < P::R1; ++i) {
+        const int k = LineOut<P, N>::k(j0, i);
+        if ((k - z0 + N) % N < nz) F[lbase + k] = v[i];
+      }
+    }
+  };
+  // line groups blockIdx.x, blockIdx.x + gridDim.x, ...: the next group's loads are in flight
+  // during this group's transform and stores
   C<T> v[P::R1];
-  if (MODE == R2C_PAD) {
-    const T* rho = reinterpret_cast<const T*>(in);
-    const double s01 = D0[o0] * D1[o1];
-    const int64_t rb = (static_cast<int64_t>(o0) * n1 + o1) * nc2;
+  int g = blockIdx.x;
+  load(g, v);
+  for (;;) {
+    const int gn = g + static_cast<int>(gridDim.x);
+    C<T> nx[P::R1];
+    if (gn < ngroups) load(gn, nx);
+    line_fft<T, N, SIGN, P, kWave>(my, addr, j0, tw, v);
+    store(g, v);
+    if (gn >= ngroups) break;
 #pragma unroll
-    for (int r = 0; r < P::R1; ++r) {
-      const int k = j0 + r * TL;
-      if (valid && active(k, N, nc2)) {
-        const int c2 = cmap(k, N, nc2);
-        v[r] = C<T>{static_cast<T>(static_cast<double>(rho[rb + c2]) * s01 * D2[c2]), T(0)};
-      } else {
-        v[r] = C<T>{0, 0};
-      }
-    }
-  } else {
-    const C<T>* F = reinterpret_cast<const C<T>*>(in);
-    int64_t lbase;
-    if (MODE == C2C) lbase = static_cast<int64_t>(line) * N;
-    else lbase = (static_cast<int64_t>(fmap(o0, d0, n0)) * d1 + fmap(o1, d1, n1)) * N;
-#pragma unroll
-    for (int r = 0; r < P::R1; ++r) {
-      const int k = j0 + r * TL;
-      v[r] = valid && (k - z0 + N) % N < nz ? F[lbase + k] : C<T>{0, 0};
-    }
-  }
-  line_fft<T, N, SIGN, P>(my, addr, j0, tw, v);
-  if (!valid) return;
-  if (MODE == C2R_TRUNC || MODE == C2R_ADD) {
-    T* phi = reinterpret_cast<T*>(out);
-    const double s01 = D0[o0] * D1[o1];
-    const int64_t rb = (static_cast<int64_t>(o0) * n1 + o1) * nc2;
-#pragma unroll
-    for (int i = 0; i < P::R1; ++i) {
-      const int k = LineOut<P, N>::k(j0, i);
-      if (active(k, N, nc2)) {
-        const int c2 = cmap(k, N, nc2);
-        const T val = static_cast<T>(static_cast<double>(v[i].re) * s01 * D2[c2]);
-        if (MODE == C2R_ADD) phi[rb + c2] += val;
-        else phi[rb + c2] = val;
-      }
-    }
-  } else {
-    C<T>* F = reinterpret_cast<C<T>*>(out);
-    int64_t lbase;
-    if (MODE == C2C) lbase = static_cast<int64_t>(line) * N;
-    else lbase = (static_cast<int64_t>(fmap(o0, d0, n0)) * d1 + fmap(o1, d1, n1)) * N;
-#pragma unroll
-    for (int i = 0; i < P::R1; ++i) {
-      const int k = LineOut<P, N>::k(j0, i);
-      if ((k - z0 + N) % N < nz) F[lbase + k] = v[i];
-    }
+    for (int r = 0; r < P::R1; ++r) v[r] = nx[r];
+    g = gn;
+    lds_sync<kWave>();                       // the last exchange's reads precede the next writes
   }
 }
 
@@ -509,7 +560,9 @@ static hipError_t launch_contig_n(const void* in, void* out, int n0, int n1, int
   while (B > 1 && static_cast<size_t>(B) * LS * sizeof(LdsElem<T, N>) > 65536) B >>= 1;
   const int nlines = n0 * n1;
   const size_t shm = static_cast<size_t>(B) * LS * sizeof(LdsElem<T, N>);
-  const int blocks = (nlines + B - 1) / B;
+  const int ngroups = (nlines + B - 1) / B;
+  const int blocks = kContigBlocks < 0 ? std::min(ngroups, std::max(512, std::min(1024, ngroups / 4)))
+                     : kContigBlocks > 0 ? std::min(ngroups, kContigBlocks) : ngroups;
   hipLaunchKernelGGL((k_fft_contig<T, N, SIGN, MODE>), dim3(blocks), dim3(B * TL), shm, s, in, out, n0, n1, d0, d1,
                      nc2, z0, nz, D0, D1, D2, tw, B, nlines);
   return hipGetLastError();

@@ -696,6 +696,11 @@ __global__ void __launch_bounds__(64) k_interp_mfma(const C<T>* __restrict__ F, 
   const int kk = lane >> 4, col = lane & 15, xo = col >> 1;
   const int yo = 4 * (kk >> 1), zo = 4 * (kk & 1);
   const bool b3 = (lane & 8) != 0, b2 = (lane & 4) != 0;
+#if DDI_INTERP_BREG
+  double bfr[16];                            // the lane's B fragments, the same for every block
+#pragma unroll
+  for (int st = 0; st < 16; ++st) bfr[st] = fragB[st * SB + lane];
+#endif
   for (int mb = 0; mb < nmb; ++mb) {
     double wy[4], wz[4];
 #pragma unroll
@@ -715,7 +720,11 @@ __global__ void __launch_bounds__(64) k_interp_mfma(const C<T>* __restrict__ F, 
     dbl4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int st = 0; st < 16; ++st)
+#if DDI_INTERP_BREG
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(wy[st >> 2] * wz[st & 3], bfr[st], acc, 0, 0, 0);
+#else
       acc = __builtin_amdgcn_mfma_f64_16x16x4f64(wy[st >> 2] * wz[st & 3], fragB[st * SB + lane], acc, 0, 0, 0);
+#endif
     // item i holds row 4 i + kk (entry 16 mb + 4 i + kk), an A row of lane (4 i + kk) + 16 (xo / 2)
     double v[4];
 #pragma unroll
@@ -782,15 +791,24 @@ __global__ void __launch_bounds__(256) k_interp_gather(const C<double>* __restri
   out[q] = C<T>{static_cast<T>(s * sr), static_cast<T>(s * si)};
 }
 
-// Sum the partial tiles of each split tile in slot order (deterministic); one thread per point,
-// kReduceSplit workgroups per tile (a hot tile's hundred slots are then read by several CUs).
+// Sum the partial tiles of each split tile (deterministic): kReduceSplit workgroups per tile
+// (a hot tile's slots are then read by several CUs), each taking a part of the tile's points
+// with kReduceGroups threads per point; thread group u sums the slots u, u + G, u + 2G, ... in
+// order, sixteen loads in flight, and the G sums are added in group order.
 constexpr int kReduceSplit = 4;
+#ifndef DDI_REDUCE_GROUPS
+#define DDI_REDUCE_GROUPS 4
+#endif
+constexpr int kReduceGroups = DDI_REDUCE_GROUPS;
+constexpr int kReducePoints = 64 * kTileZ / kReduceSplit;   // points per workgroup
 template <typename T, int TX, int TY>
-__global__ void __launch_bounds__(64 * kTileZ / kReduceSplit) k_spread_reduce(C<T>* __restrict__ F,
+__global__ void __launch_bounds__(kReducePoints * kReduceGroups) k_spread_reduce(C<T>* __restrict__ F,
                                                                const C<T>* __restrict__ partial,
                                                                const ReduceItem* __restrict__ red, int nf1, int nf2,
                                                                int nt1, int nt2) {
-  const int pt = (blockIdx.x % kReduceSplit) * (64 * kTileZ / kReduceSplit) + threadIdx.x;   // point of the tile
+  constexpr int G = kReduceGroups;
+  const int u = threadIdx.x / kReducePoints;
+  const int pt = (blockIdx.x % kReduceSplit) * kReducePoints + threadIdx.x % kReducePoints;   // point of the tile
   const int lane = pt & 63;
   const int i = pt >> 6;
   const ReduceItem r = red[blockIdx.x / kReduceSplit];
@@ -799,34 +817,48 @@ __global__ void __launch_bounds__(64 * kTileZ / kReduceSplit) k_spread_reduce(C<
   const int tx = r.tile / (nt2 * nt1);
   const int x = tx * TX + lane / TY, y = ty * TY + lane % TY, z = tz * kTileZ + i;
   const C<T>* src = partial + (static_cast<int64_t>(r.first_slot) * kTileZ + i) * 64 + lane;
-  // sixteen loads in flight (hot tiles of a small ball of nodes have a hundred slots and more);
-  // the sum stays in slot order
+  constexpr int64_t kSlot = 64 * kTileZ;     // elements per slot
   double sr = 0.0, si = 0.0;
-  int s = 0;
-  for (; s + 16 <= r.nslots; s += 16) {
+  int s = u;
+  for (; s + 15 * G < r.nslots; s += 16 * G) {
     C<T> v[16];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) v[j] = src[static_cast<int64_t>(s + j) * 64 * kTileZ];
+    for (int j = 0; j < 16; ++j) v[j] = src[static_cast<int64_t>(s + j * G) * kSlot];
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       sr += static_cast<double>(v[j].re);
       si += static_cast<double>(v[j].im);
     }
   }
-  for (; s + 4 <= r.nslots; s += 4) {
+  for (; s + 3 * G < r.nslots; s += 4 * G) {
     C<T> v[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) v[j] = src[static_cast<int64_t>(s + j) * 64 * kTileZ];
+    for (int j = 0; j < 4; ++j) v[j] = src[static_cast<int64_t>(s + j * G) * kSlot];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       sr += static_cast<double>(v[j].re);
       si += static_cast<double>(v[j].im);
     }
   }
-  for (; s < r.nslots; ++s) {
-    const C<T> v = src[static_cast<int64_t>(s) * 64 * kTileZ];
+  for (; s < r.nslots; s += G) {
+    const C<T> v = src[static_cast<int64_t>(s) * kSlot];
     sr += static_cast<double>(v.re);
     si += static_cast<double>(v.im);
+  }
+  if constexpr (G > 1) {
+    __shared__ double part[G > 1 ? G - 1 : 1][kReducePoints][2];
+    const int p = threadIdx.x % kReducePoints;
+    if (u > 0) {
+      part[u - 1][p][0] = sr;
+      part[u - 1][p][1] = si;
+    }
+    __syncthreads();
+    if (u > 0) return;
+#pragma unroll
+    for (int g = 0; g < G - 1; ++g) {
+      sr += part[g][p][0];
+      si += part[g][p][1];
+    }
   }
   F[(static_cast<int64_t>(x) * nf1 + y) * nf2 + z] = C<T>{static_cast<T>(sr), static_cast<T>(si)};
 }
@@ -1028,7 +1060,7 @@ static hipError_t spread_t(DevicePlan& P, int which, const C<T>* g, hipStream_t 
   DDI_REC(5);
   if (!S.reduces.empty()) {
     hipLaunchKernelGGL((k_spread_reduce<T, TX, TY>), dim3(static_cast<int>(S.reduces.size()) * kReduceSplit),
-                       dim3(64 * kTileZ / kReduceSplit), 0,
+                       dim3(kReducePoints * kReduceGroups), 0,
                        s, F, reinterpret_cast<const C<T>*>(P.partial), D.reduces, H.nf[1], H.nf[2], H.ntiles[1],
                        H.ntiles[2]);
     DDI_CHECK(hipGetLastError());
