@@ -42,6 +42,12 @@ constexpr int kContigThreads = DDI_CONTIG_THREADS;
 // groups, at least 512 (or all of them) and at most 1024; 0: one per line group; n > 0: n.
 // Wave-local LDS barriers where a line lies inside one wave.
 constexpr int kContigBlocks = DDI_CONTIG_BLOCKS;
+#ifndef DDI_STRIDED_BLOCKS
+#define DDI_STRIDED_BLOCKS 512
+#endif
+// workgroups of a strided pass (0: one per line bundle), each looping over bundles with the next
+// bundle's loads in flight
+constexpr int kStridedBlocks = DDI_STRIDED_BLOCKS;
 constexpr bool kContigWaveSync = DDI_CONTIG_WAVESYNC != 0;
 
 // ------------------------------------------------------------------ radix plans
@@ -216,27 +222,51 @@ __global__ void __launch_bounds__(MAXT) k_fft_strided(C<T>* __restrict__ F, int 
   constexpr int TL = N / P::R1;
   const int b = threadIdx.x % B;
   const int j0 = threadIdx.x / B;
-  const int blk = blockIdx.x;
-  const int o = blk / nzb;
-  const int z = (z0 + (blk % nzb) * B) % d2 + b;   // z0 is a multiple of B
   const int d_o = axis == 0 ? d1 : d0;
-  const int of = o_compact ? fmap(o, d_o, n_o) : o;
-  int64_t base, stride;
-  if (axis == 0) { base = static_cast<int64_t>(of) * d2 + z; stride = static_cast<int64_t>(d1) * d2; }
-  else { base = static_cast<int64_t>(of) * d1 * d2 + z; stride = d2; }
+  const int nblk = n_o * nzb;
+  const int64_t stride = axis == 0 ? static_cast<int64_t>(d1) * d2 : d2;
+  // first element of the thread's line in line bundle blk
+  auto line_base = [&](int blk) -> int64_t {
+    const int o = blk / nzb;
+    const int z = (z0 + (blk % nzb) * B) % d2 + b;   // z0 is a multiple of B
+    const int of = o_compact ? fmap(o, d_o, n_o) : o;
+    return axis == 0 ? static_cast<int64_t>(of) * d2 + z : static_cast<int64_t>(of) * d1 * d2 + z;
+  };
+  auto load = [&](int64_t base, C<T>* v) {
+#pragma unroll
+    for (int r = 0; r < P::R1; ++r) {
+      const int k = j0 + r * TL;
+      if (in_compact && !active(k, N, nc_axis)) v[r] = C<T>{0, 0};
+      else v[r] = F[base + k * stride];
+    }
+  };
   auto addr = [B, b](int k) { return k * B + b; };
+  // bundles blockIdx.x, blockIdx.x + gridDim.x, ...: the next bundle's loads are in flight during
+  // this bundle's transform and stores (bundles are disjoint sets of lines)
+  int blk = blockIdx.x;
+  int64_t base = line_base(blk);
   C<T> v[P::R1];
+  load(base, v);
+  for (;;) {
+    const int nb = blk + static_cast<int>(gridDim.x);
+    C<T> nx[P::R1];
+    int64_t nbase = 0;
+    if (nb < nblk) {
+      nbase = line_base(nb);
+      load(nbase, nx);
+    }
+    line_fft<T, N, SIGN, P>(lds, addr, j0, tw, v);
 #pragma unroll
-  for (int r = 0; r < P::R1; ++r) {
-    const int k = j0 + r * TL;
-    if (in_compact && !active(k, N, nc_axis)) v[r] = C<T>{0, 0};
-    else v[r] = F[base + k * stride];
-  }
-  line_fft<T, N, SIGN, P>(lds, addr, j0, tw, v);
+    for (int i = 0; i < P::R1; ++i) {
+      const int k = LineOut<P, N>::k(j0, i);
+      if (!out_compact || active(k, N, nc_out)) F[base + k * stride] = v[i];
+    }
+    if (nb >= nblk) break;
 #pragma unroll
-  for (int i = 0; i < P::R1; ++i) {
-    const int k = LineOut<P, N>::k(j0, i);
-    if (!out_compact || active(k, N, nc_out)) F[base + k * stride] = v[i];
+    for (int r = 0; r < P::R1; ++r) v[r] = nx[r];
+    base = nbase;
+    blk = nb;
+    __syncthreads();                         // the last exchange's reads precede the next writes
   }
 }
 
@@ -471,8 +501,9 @@ static hipError_t launch_strided_n(C<T>* F, int axis, int d0, int d1, int d2, in
     return hipErrorInvalidValue;
   const size_t shm = static_cast<size_t>(B) * N * sizeof(LdsElem<T, N>);
   const int nzb = nz / B;
-  const int blocks = n_o * nzb;
-  if (blocks == 0) return hipSuccess;
+  const int nblk = n_o * nzb;
+  if (nblk == 0) return hipSuccess;
+  const int blocks = kStridedBlocks > 0 ? std::min(nblk, kStridedBlocks) : nblk;
   if (B * TL <= 256)
     hipLaunchKernelGGL((k_fft_strided<T, N, SIGN, 256>), dim3(blocks), dim3(B * TL), shm, s, F, axis, d0, d1, d2,
                        n_o, o_compact, nc, in_c, out_c, nc_out, z0, nzb, tw, B);

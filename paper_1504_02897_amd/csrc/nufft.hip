@@ -437,6 +437,14 @@ __device__ inline double row_load(__amdgpu_buffer_rsrc_t rows, unsigned off) {
     return static_cast<double>(__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rows, off, 0, 0)));
 }
 
+// LDS barrier of a one-wave workgroup: LDS operations of a wave complete in order; the fences
+// keep the compiler from moving them across.
+__device__ __forceinline__ void lds_sync_wave() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Matrix-core form of the spread (FP64, 3D, weight rows): for a tile
 //   D[(y,z)][(x,p)] = sum_e A[e][(y,z)] Bs[e][(x,p)],  A[e][(y,z)] = wy_e[y] wz_e[z],
 //   Bs[e][(x,p)] = wx_e[x] (part p of g_e),
@@ -471,7 +479,9 @@ __global__ void __launch_bounds__(64, 4) k_spread_mfma(C<T>* __restrict__ F, C<T
   // one LDS buffer: the stage weights and node values while entries are accumulated, then the
   // output tile (after the last stage)
   constexpr int XS = 136;                    // x stride of the output staging (bank spread)
-  __shared__ double lds[8 * XS];
+  constexpr int XH = 4;                      // x rows of the output staged at once (half the LDS of
+                                             // the whole tile: more workgroups per CU)
+  __shared__ double lds[XH * XS];
   double* wts = lds;                         // [entry of the stage][axis][8 tile positions]
   double* gv = lds + 16 * 24;                // [entry of the stage][part]
   double* tileO = lds;                       // [x][y][z][part]
@@ -502,7 +512,7 @@ __global__ void __launch_bounds__(64, 4) k_spread_mfma(C<T>* __restrict__ F, C<T
     load_stage(0, raw, graw);
     publish(raw, graw);
   }
-  __syncthreads();
+  lds_sync_wave();
   const int k = lane >> 4, i = lane & 15, x = i >> 1, p = i & 1;
   dbl4s acc[4];
 #pragma unroll
@@ -521,33 +531,39 @@ __global__ void __launch_bounds__(64, 4) k_spread_mfma(C<T>* __restrict__ F, C<T
         acc[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(we[8 + 2 * mb + (i >> 3)] * wzv, b, acc[mb], 0, 0, 0);
     }
     if (more) {
-      __syncthreads();                       // every lane has read this stage's weights
+      lds_sync_wave();                       // every lane has read this stage's weights
       publish(raw, graw);
-      __syncthreads();
+      lds_sync_wave();
     }
   }
-  __syncthreads();                           // the last stage's weights are no longer read
-  // item t of block mb: row 4 t + k -> (y, z) = (2 mb + t / 2, 4 (t % 2) + k), column (x, p)
+  // item t of block mb: row 4 t + k -> (y, z) = (2 mb + t / 2, 4 (t % 2) + k), column (x, p);
+  // x rows [XH h, XH h + XH) go through LDS at a time and are written eight lanes per 128-byte
+  // row along the last axis (or to the partial slot, in k_spread's slot layout)
+  const int zl = lane & 7;
 #pragma unroll
-  for (int mb = 0; mb < 4; ++mb) {
+  for (int h = 0; h < 8 / XH; ++h) {
+    lds_sync_wave();                         // earlier reads of the buffer are done
+    if (x / XH == h) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int y = 2 * mb + (t >> 1), z = 4 * (t & 1) + k;
-      tileO[x * XS + (y * 8 + z) * 2 + p] = acc[mb][t];
+      for (int mb = 0; mb < 4; ++mb) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int y = 2 * mb + (t >> 1), z = 4 * (t & 1) + k;
+          tileO[(x % XH) * XS + (y * 8 + z) * 2 + p] = acc[mb][t];
+        }
+      }
     }
-  }
-  __syncthreads();
-  // eight lanes per 128-byte row: store r covers columns 8 r .. 8 r + 7, lane & 7 = z
-  const int z = lane & 7;
+    lds_sync_wave();
 #pragma unroll
-  for (int r = 0; r < 8; ++r) {
-    const int c = 8 * r + (lane >> 3), cx = c >> 3, cy = c & 7;
-    const double* o = tileO + cx * XS + (cy * 8 + z) * 2;
-    const C<T> v = C<T>{static_cast<T>(o[0]), static_cast<T>(o[1])};
-    if (it.slot < 0)
-      F[(static_cast<int64_t>(tx * 8 + cx) * nf1 + (ty * 8 + cy)) * nf2 + tz * kTileZ + z] = v;
-    else
-      partial[static_cast<int64_t>(it.slot) * 64 * kTileZ + z * 64 + c] = v;
+    for (int rr = 0; rr < XH; ++rr) {
+      const int c = 8 * (XH * h + rr) + (lane >> 3), cx = c >> 3, cy = c & 7;
+      const double* o = tileO + (cx % XH) * XS + (cy * 8 + zl) * 2;
+      const C<T> v = C<T>{static_cast<T>(o[0]), static_cast<T>(o[1])};
+      if (it.slot < 0)
+        F[(static_cast<int64_t>(tx * 8 + cx) * nf1 + (ty * 8 + cy)) * nf2 + tz * kTileZ + zl] = v;
+      else
+        partial[static_cast<int64_t>(it.slot) * 64 * kTileZ + zl * 64 + c] = v;
+    }
   }
 }
 
