@@ -43,10 +43,11 @@ constexpr int kContigThreads = DDI_CONTIG_THREADS;
 // Wave-local LDS barriers where a line lies inside one wave.
 constexpr int kContigBlocks = DDI_CONTIG_BLOCKS;
 #ifndef DDI_STRIDED_BLOCKS
-#define DDI_STRIDED_BLOCKS 512
+#define DDI_STRIDED_BLOCKS -1
 #endif
-// workgroups of a strided pass (0: one per line bundle), each looping over bundles with the next
-// bundle's loads in flight
+// Workgroups of a strided pass, each looping over line bundles with the next bundle's loads in
+// flight.  -1: 131072 threads' worth, clamped to [256, 512] workgroups (512 of 256 threads, 256
+// of 1024); 0: one per bundle; n > 0: n.
 constexpr int kStridedBlocks = DDI_STRIDED_BLOCKS;
 constexpr bool kContigWaveSync = DDI_CONTIG_WAVESYNC != 0;
 
@@ -503,7 +504,8 @@ static hipError_t launch_strided_n(C<T>* F, int axis, int d0, int d1, int d2, in
   const int nzb = nz / B;
   const int nblk = n_o * nzb;
   if (nblk == 0) return hipSuccess;
-  const int blocks = kStridedBlocks > 0 ? std::min(nblk, kStridedBlocks) : nblk;
+  const int blocks = kStridedBlocks < 0 ? std::min(nblk, std::max(256, std::min(512, 131072 / (B * TL))))
+                     : kStridedBlocks > 0 ? std::min(nblk, kStridedBlocks) : nblk;
   if (B * TL <= 256)
     hipLaunchKernelGGL((k_fft_strided<T, N, SIGN, 256>), dim3(blocks), dim3(B * TL), shm, s, F, axis, d0, d1, d2,
                        n_o, o_compact, nc, in_c, out_c, nc_out, z0, nzb, tw, B);
