@@ -212,7 +212,7 @@ __device__ __forceinline__ int cmap(int k, int n, int nc) { return k < nc - nc /
 // z per workgroup.  The other non-z axis runs over n_o lines (compact when
 // o_compact: index o -> fine index fmap(o, d_o, n_o)).  in_compact / out_compact:
 // only the nc_axis / nc_out active positions of the line are read (rest zero) / written.
-template <typename T, int N, int SIGN, int MAXT>
+template <typename T, int N, int SIGN, int MAXT, bool PF>
 __global__ void __launch_bounds__(MAXT) k_fft_strided(C<T>* __restrict__ F, int axis, int d0, int d1, int d2,
                                                      int n_o, int o_compact, int nc_axis, int in_compact,
                                                      int out_compact, int nc_out, int z0, int nzb,
@@ -242,17 +242,18 @@ __global__ void __launch_bounds__(MAXT) k_fft_strided(C<T>* __restrict__ F, int 
     }
   };
   auto addr = [B, b](int k) { return k * B + b; };
-  // bundles blockIdx.x, blockIdx.x + gridDim.x, ...: the next bundle's loads are in flight during
-  // this bundle's transform and stores (bundles are disjoint sets of lines)
+  // bundles blockIdx.x, blockIdx.x + gridDim.x, ...: with PF the next bundle's loads are in flight
+  // during this bundle's transform and stores (bundles are disjoint sets of lines); without, the
+  // grid covers every bundle once (no second register set)
   int blk = blockIdx.x;
   int64_t base = line_base(blk);
   C<T> v[P::R1];
   load(base, v);
   for (;;) {
     const int nb = blk + static_cast<int>(gridDim.x);
-    C<T> nx[P::R1];
+    C<T> nx[PF ? P::R1 : 1];
     int64_t nbase = 0;
-    if (nb < nblk) {
+    if (PF && nb < nblk) {
       nbase = line_base(nb);
       load(nbase, nx);
     }
@@ -262,9 +263,9 @@ __global__ void __launch_bounds__(MAXT) k_fft_strided(C<T>* __restrict__ F, int 
       const int k = LineOut<P, N>::k(j0, i);
       if (!out_compact || active(k, N, nc_out)) F[base + k * stride] = v[i];
     }
-    if (nb >= nblk) break;
+    if (!PF || nb >= nblk) break;
 #pragma unroll
-    for (int r = 0; r < P::R1; ++r) v[r] = nx[r];
+    for (int r = 0; r < (PF ? P::R1 : 1); ++r) v[r] = nx[r];
     base = nbase;
     blk = nb;
     __syncthreads();                         // the last exchange's reads precede the next writes
@@ -383,7 +384,7 @@ __global__ void __launch_bounds__(MAXT, 1024 / MAXT) k_fft_symbol(C<T>* __restri
 // deconvolution factors, placed at the active positions of a length-N line,
 // output complex line.  C2R_TRUNC: input complex line, output
 // Re(line[fmap(c2)]) times the deconvolution factors into phi[N0][N1][N2].
-template <typename T, int N, int SIGN, int MODE>
+template <typename T, int N, int SIGN, int MODE, bool PF>
 __global__ void __launch_bounds__(kContigThreads) k_fft_contig(const void* in, void* out,
                                                     int n0, int n1, int d0, int d1, int nc2, int z0, int nz,
                                                     const double* __restrict__ D0, const double* __restrict__ D1,
@@ -463,20 +464,20 @@ __global__ void __launch_bounds__(kContigThreads) k_fft_contig(const void* in, v
       }
     }
   };
-  // line groups blockIdx.x, blockIdx.x + gridDim.x, ...: the next group's loads are in flight
-  // during this group's transform and stores
+  // line groups blockIdx.x, blockIdx.x + gridDim.x, ...: with PF the next group's loads are in
+  // flight during this group's transform and stores; without, the grid covers every group once
   C<T> v[P::R1];
   int g = blockIdx.x;
   load(g, v);
   for (;;) {
     const int gn = g + static_cast<int>(gridDim.x);
-    C<T> nx[P::R1];
-    if (gn < ngroups) load(gn, nx);
+    C<T> nx[PF ? P::R1 : 1];
+    if (PF && gn < ngroups) load(gn, nx);
     line_fft<T, N, SIGN, P, kWave>(my, addr, j0, tw, v);
     store(g, v);
-    if (gn >= ngroups) break;
+    if (!PF || gn >= ngroups) break;
 #pragma unroll
-    for (int r = 0; r < P::R1; ++r) v[r] = nx[r];
+    for (int r = 0; r < (PF ? P::R1 : 1); ++r) v[r] = nx[r];
     g = gn;
     lds_sync<kWave>();                       // the last exchange's reads precede the next writes
   }
@@ -506,12 +507,19 @@ static hipError_t launch_strided_n(C<T>* F, int axis, int d0, int d1, int d2, in
   if (nblk == 0) return hipSuccess;
   const int blocks = kStridedBlocks < 0 ? std::min(nblk, std::max(256, std::min(512, 131072 / (B * TL))))
                      : kStridedBlocks > 0 ? std::min(nblk, kStridedBlocks) : nblk;
-  if (B * TL <= 256)
-    hipLaunchKernelGGL((k_fft_strided<T, N, SIGN, 256>), dim3(blocks), dim3(B * TL), shm, s, F, axis, d0, d1, d2,
-                       n_o, o_compact, nc, in_c, out_c, nc_out, z0, nzb, tw, B);
+  const bool pf = blocks < nblk;
+  if (B * TL <= 256 && pf)
+    hipLaunchKernelGGL((k_fft_strided<T, N, SIGN, 256, true>), dim3(blocks), dim3(B * TL), shm, s, F, axis, d0, d1,
+                       d2, n_o, o_compact, nc, in_c, out_c, nc_out, z0, nzb, tw, B);
+  else if (B * TL <= 256)
+    hipLaunchKernelGGL((k_fft_strided<T, N, SIGN, 256, false>), dim3(blocks), dim3(B * TL), shm, s, F, axis, d0, d1,
+                       d2, n_o, o_compact, nc, in_c, out_c, nc_out, z0, nzb, tw, B);
+  else if (pf)
+    hipLaunchKernelGGL((k_fft_strided<T, N, SIGN, 1024, true>), dim3(blocks), dim3(B * TL), shm, s, F, axis, d0, d1,
+                       d2, n_o, o_compact, nc, in_c, out_c, nc_out, z0, nzb, tw, B);
   else
-    hipLaunchKernelGGL((k_fft_strided<T, N, SIGN, 1024>), dim3(blocks), dim3(B * TL), shm, s, F, axis, d0, d1, d2,
-                       n_o, o_compact, nc, in_c, out_c, nc_out, z0, nzb, tw, B);
+    hipLaunchKernelGGL((k_fft_strided<T, N, SIGN, 1024, false>), dim3(blocks), dim3(B * TL), shm, s, F, axis, d0, d1,
+                       d2, n_o, o_compact, nc, in_c, out_c, nc_out, z0, nzb, tw, B);
   return hipGetLastError();
 }
 
@@ -596,8 +604,12 @@ static hipError_t launch_contig_n(const void* in, void* out, int n0, int n1, int
   const int ngroups = (nlines + B - 1) / B;
   const int blocks = kContigBlocks < 0 ? std::min(ngroups, std::max(512, std::min(1024, ngroups / 4)))
                      : kContigBlocks > 0 ? std::min(ngroups, kContigBlocks) : ngroups;
-  hipLaunchKernelGGL((k_fft_contig<T, N, SIGN, MODE>), dim3(blocks), dim3(B * TL), shm, s, in, out, n0, n1, d0, d1,
-                     nc2, z0, nz, D0, D1, D2, tw, B, nlines);
+  if (blocks < ngroups)
+    hipLaunchKernelGGL((k_fft_contig<T, N, SIGN, MODE, true>), dim3(blocks), dim3(B * TL), shm, s, in, out, n0, n1,
+                       d0, d1, nc2, z0, nz, D0, D1, D2, tw, B, nlines);
+  else
+    hipLaunchKernelGGL((k_fft_contig<T, N, SIGN, MODE, false>), dim3(blocks), dim3(B * TL), shm, s, in, out, n0, n1,
+                       d0, d1, nc2, z0, nz, D0, D1, D2, tw, B, nlines);
   return hipGetLastError();
 }
 
