@@ -401,25 +401,37 @@ __global__ void __launch_bounds__(kContigThreads) k_fft_contig(const void* in, v
   const int ngroups = (nlines + B - 1) / B;
   LdsElem<T, N>* my = lds + lb * LS;
   auto addr = [](int k) { return k + k / Radix<T, N, true>::R1; };
-  // the thread's inputs of line group g (zeros outside the line's active or windowed positions)
-  auto load = [&](int g, C<T>* v) {
+  // Deconvolution factors along the last axis at the thread's positions (inputs for R2C_PAD,
+  // outputs for C2R_*): the same for every line, loaded once.  The line's factor D0 D1 is loaded
+  // with the line's inputs and applied only when the line is transformed or stored, so that a
+  // prefetched group's loads are not waited for ahead of the current group's transform.
+  constexpr bool kIn = MODE == R2C_PAD, kOut = MODE == C2R_TRUNC || MODE == C2R_ADD;
+  double d2f[(kIn || kOut) ? P::R1 : 1];
+  if constexpr (kIn || kOut) {
+#pragma unroll
+    for (int r = 0; r < P::R1; ++r) {
+      const int k = kIn ? j0 + r * TL : LineOut<P, N>::k(j0, r);
+      d2f[r] = active(k, N, nc2) ? D2[cmap(k, N, nc2)] : 0.0;
+    }
+  }
+  // the thread's raw inputs of line group g (zeros outside the line's active or windowed
+  // positions) and the line's D0, D1
+  auto load = [&](int g, C<T>* v, double* f01) {
     const int line = g * B + lb;
     const bool valid = line < nlines;
     const int o0 = valid ? line / n1 : 0;
     const int o1 = valid ? line % n1 : 0;
+    if constexpr (kIn || kOut) {
+      f01[0] = D0[o0];
+      f01[1] = D1[o1];
+    }
     if (MODE == R2C_PAD) {
       const T* rho = reinterpret_cast<const T*>(in);
-      const double s01 = D0[o0] * D1[o1];
       const int64_t rb = (static_cast<int64_t>(o0) * n1 + o1) * nc2;
 #pragma unroll
       for (int r = 0; r < P::R1; ++r) {
         const int k = j0 + r * TL;
-        if (valid && active(k, N, nc2)) {
-          const int c2 = cmap(k, N, nc2);
-          v[r] = C<T>{static_cast<T>(static_cast<double>(rho[rb + c2]) * s01 * D2[c2]), T(0)};
-        } else {
-          v[r] = C<T>{0, 0};
-        }
+        v[r] = valid && active(k, N, nc2) ? C<T>{rho[rb + cmap(k, N, nc2)], T(0)} : C<T>{0, 0};
       }
     } else {
       const C<T>* F = reinterpret_cast<const C<T>*>(in);
@@ -433,23 +445,22 @@ __global__ void __launch_bounds__(kContigThreads) k_fft_contig(const void* in, v
       }
     }
   };
-  auto store = [&](int g, const C<T>* v) {
+  auto store = [&](int g, const C<T>* v, const double* f01) {
     const int line = g * B + lb;
     if (line >= nlines) return;
     const int o0 = line / n1;
     const int o1 = line % n1;
-    if (MODE == C2R_TRUNC || MODE == C2R_ADD) {
+    if constexpr (kOut) {
       T* phi = reinterpret_cast<T*>(out);
-      const double s01 = D0[o0] * D1[o1];
+      const double s01 = f01[0] * f01[1];
       const int64_t rb = (static_cast<int64_t>(o0) * n1 + o1) * nc2;
 #pragma unroll
       for (int i = 0; i < P::R1; ++i) {
         const int k = LineOut<P, N>::k(j0, i);
         if (active(k, N, nc2)) {
-          const int c2 = cmap(k, N, nc2);
-          const T val = static_cast<T>(static_cast<double>(v[i].re) * s01 * D2[c2]);
-          if (MODE == C2R_ADD) phi[rb + c2] += val;
-          else phi[rb + c2] = val;
+          const T val = static_cast<T>(static_cast<double>(v[i].re) * s01 * d2f[i]);
+          if (MODE == C2R_ADD) phi[rb + cmap(k, N, nc2)] += val;
+          else phi[rb + cmap(k, N, nc2)] = val;
         }
       }
     } else {
@@ -467,17 +478,26 @@ __global__ void __launch_bounds__(kContigThreads) k_fft_contig(const void* in, v
   // line groups blockIdx.x, blockIdx.x + gridDim.x, ...: with PF the next group's loads are in
   // flight during this group's transform and stores; without, the grid covers every group once
   C<T> v[P::R1];
+  double f01[2] = {0.0, 0.0};
   int g = blockIdx.x;
-  load(g, v);
+  load(g, v, f01);
   for (;;) {
     const int gn = g + static_cast<int>(gridDim.x);
     C<T> nx[PF ? P::R1 : 1];
-    if (PF && gn < ngroups) load(gn, nx);
+    double nf01[2] = {0.0, 0.0};
+    if (PF && gn < ngroups) load(gn, nx, nf01);
+    if constexpr (kIn) {
+      const double s01 = f01[0] * f01[1];
+#pragma unroll
+      for (int r = 0; r < P::R1; ++r) v[r].re = static_cast<T>(static_cast<double>(v[r].re) * s01 * d2f[r]);
+    }
     line_fft<T, N, SIGN, P, kWave>(my, addr, j0, tw, v);
-    store(g, v);
+    store(g, v, f01);
     if (!PF || gn >= ngroups) break;
 #pragma unroll
     for (int r = 0; r < (PF ? P::R1 : 1); ++r) v[r] = nx[r];
+    f01[0] = nf01[0];
+    f01[1] = nf01[1];
     g = gn;
     lds_sync<kWave>();                       // the last exchange's reads precede the next writes
   }
