@@ -42,6 +42,7 @@ constexpr int kContigThreads = DDI_CONTIG_THREADS;
 // groups, at least 512 (or all of them) and at most 1024; 0: one per line group; n > 0: n.
 // Wave-local LDS barriers where a line lies inside one wave.
 constexpr int kContigBlocks = DDI_CONTIG_BLOCKS;
+
 #ifndef DDI_STRIDED_BLOCKS
 #define DDI_STRIDED_BLOCKS -1
 #endif
@@ -70,11 +71,13 @@ template <> struct RadixPlan<96> { static constexpr int R1 = 12, R2 = 4, R3 = 2,
 template <> struct RadixPlan<192> { static constexpr int R1 = 12, R2 = 4, R3 = 4, R4 = 1; };
 template <> struct RadixPlan<384> { static constexpr int R1 = 12, R2 = 4, R3 = 4, R4 = 2; };
 template <> struct RadixPlan<768> { static constexpr int R1 = 12, R2 = 4, R3 = 4, R4 = 4; };
-// Plan per element type and pass kind: FP64 256-point lines along the contiguous axis use
-// radix 8 x 8 x 4 (eight values per thread: half the registers of radix 16, one more LDS
-// exchange); measured slower for the strided passes, which keep radix 16 x 16.
+// Plan per element type and pass kind: FP64 256-point lines use radix 8 x 8 x 4 (eight values
+// per thread: half the registers of radix 16, one more LDS exchange).  In the looping strided
+// passes the next bundle's prefetched values double the registers, so radix 16 leaves one wave
+// per SIMD there; FP32 strided lines keep radix 16 x 16 (measured faster).
 template <typename T, int N, bool CONTIG> struct Radix : RadixPlan<N> {};
 template <> struct Radix<double, 256, true> { static constexpr int R1 = 8, R2 = 8, R3 = 4, R4 = 1; };
+template <> struct Radix<double, 256, false> { static constexpr int R1 = 8, R2 = 8, R3 = 4, R4 = 1; };
 
 // FP64 lines of up to 512 points exchange the real parts through LDS, then the imaginary
 // parts: half the LDS footprint of a line (twice the resident lines per CU) for the same
