@@ -52,7 +52,7 @@ constexpr int kSpreadChunkMfma = DDI_SPREAD_CHUNK_MFMA;
 // matrix-core chunks are shortened until the entries fill about this many items (resident waves)
 constexpr int kSpreadWaves = DDI_SPREAD_WAVES;
 #ifndef DDI_SPREAD_XCD_ORDER
-#define DDI_SPREAD_XCD_ORDER 0
+#define DDI_SPREAD_XCD_ORDER 1
 #endif
 #ifndef DDI_SPREAD_UNROLL
 #define DDI_SPREAD_UNROLL 4

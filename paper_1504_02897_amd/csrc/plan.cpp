@@ -82,9 +82,10 @@ double es_fourier(double m, int nf, int w, double beta, const std::vector<double
 // each XCD works through one compact region of the grid and its L2 sees the reuse.
 // Shorter segments are padded with `pad` items, which the kernels skip.
 template <typename Item, typename Work>
-std::vector<Item> xcd_order(const std::vector<Item>& items, Work work, const Item& pad) {
+std::vector<Item> xcd_order(const std::vector<Item>& items_in, Work work, const Item& pad, bool heavy_first = false) {
   constexpr int kXcd = 8;
-  if (items.size() < 2 * kXcd) return items;
+  if (items_in.size() < 2 * kXcd) return items_in;
+  std::vector<Item> items = items_in;
   double total = 0.0;
   for (const Item& it : items) total += work(it);
   std::vector<size_t> cut(kXcd + 1, items.size());
@@ -95,6 +96,10 @@ std::vector<Item> xcd_order(const std::vector<Item>& items, Work work, const Ite
     acc += work(items[i]);
     if (acc >= total * seg / kXcd) cut[seg++] = i + 1;
   }
+  if (heavy_first)   // inside each region, the heaviest items first (the long ones start early)
+    for (int x = 0; x < kXcd; ++x)
+      std::stable_sort(items.begin() + cut[x], items.begin() + cut[x + 1],
+                       [&](const Item& a, const Item& b) { return work(a) > work(b); });
   size_t longest = 0;
   for (int x = 0; x < kXcd; ++x) longest = std::max(longest, cut[x + 1] - cut[x]);
   std::vector<Item> out(longest * kXcd, pad);
@@ -280,8 +285,14 @@ std::string build_spread_schedule(const HostTables& t, const std::vector<int64_t
     }
   }
 #if DDI_SPREAD_XCD_ORDER
-  // items are in tile order; each XCD gets one contiguous region of equal work
-  S.items = xcd_order(S.items, [](const SpreadItem& it) { return 16.0 + it.count; }, SpreadItem{-1, 0, 0, -1});
+  // items are in tile (Morton) order; each XCD gets one contiguous region of equal work, so its
+  // L2 holds the weight rows its tiles share; inside a region the heaviest items go first when
+  // items are long (about 32 entries or more on average), else the Morton order is kept
+  {
+    const bool heavy_first = count[ntile_total] >= 32 * static_cast<int64_t>(S.items.size());
+    S.items = xcd_order(S.items, [](const SpreadItem& it) { return 16.0 + it.count; }, SpreadItem{-1, 0, 0, -1},
+                        heavy_first);
+  }
 #else
   // heaviest items first so that the long ones start early
   std::stable_sort(S.items.begin(), S.items.end(),

@@ -211,8 +211,12 @@ def test_schedules_cover_every_support_once(tables, name, which):
         tid = (per_axis[0][:, None, None] * ntiles[1] + per_axis[1][None, :, None]) * ntiles[2] + per_axis[2][None, None, :]
         want.append(np.stack([tid.ravel(), np.full(tid.size, q)], 1))
     want = np.concatenate(want)
-    # (tile, node) pairs from the work items
+    # (tile, node) pairs from the work items; padding items (tile -1, no entries) only fill the
+    # per-XCD regions to equal length
     items = t[pre + "items"].reshape(-1, 4)
+    pad = items[:, 0] < 0
+    assert np.all(items[pad, 2] == 0) and np.all(items[pad, 3] == -1)
+    items = items[~pad]
     got = np.concatenate([np.stack([np.full(cnt, tl), lst[st:st + cnt]], 1) for tl, st, cnt, _ in items] + [np.zeros((0, 2), np.int64)])
     assert got.shape[0] == lst.size == want.shape[0]
     ordw = np.lexsort((want[:, 1], want[:, 0]))
