@@ -600,7 +600,7 @@ def main():
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (see the sharding notes); "
+        print("bench.py measures one GPU: the library has no multi-GPU path (one GPU per process); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
