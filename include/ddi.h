@@ -152,7 +152,7 @@ typedef struct {
   int32_t width;        /* kernel width w */
   double es_beta;       /* kernel shape parameter */
   double kmax;
-  int64_t spread_items; /* spread work items (tiles and tile chunks) */
+  int64_t spread_items; /* spread work items (tiles, tile chunks, and empty items that even out the per-XCD regions) */
   int64_t spread_entries; /* (tile, node) pairs visited by one spread */
   int64_t workspace_bytes;
   int32_t split;        /* 1 for the split of Eq. 3.9 */
