@@ -9,7 +9,25 @@ namespace ddi {
 // factors into the active half of each oversampled line; C2C is a plain complex
 // transform; C2R_TRUNC keeps the active modes, applies the deconvolution factors
 // and writes the real part to a compact grid.
-enum ContigMode { R2C_PAD = 0, C2C = 1, C2R_TRUNC = 2, C2R_ADD = 3 };   // C2R_ADD: as C2R_TRUNC, added to the output
+enum ContigMode { R2C_PAD = 0, C2C = 1, C2R_TRUNC = 2, C2R_ADD = 3,   // C2R_ADD: as C2R_TRUNC, added to the output
+                  C2C_GF_RES = 4, C2C_GF_SOLVE = 5, C2C_TS_KIN = 6 };
+
+// Elementwise steps of the gradient flow (Sec. 3.1) folded into the loads of a C2C pass over
+// an N0 x N1 x N2 grid (lines along axis 2):
+//   C2C_GF_RES:   x = (alpha - B) in, B a real grid (aux);
+//   C2C_GF_SOLVE: x = (rhs0 / dt + in) / ((1/dt + alpha + |mu|^2 / 2) prod(N)), rhs0 complex (aux),
+//                 mu_i = pi p_i / L_i with p_i the signed mode of index i on axis i (axis 0 counted
+//                 only when N0 > 1);
+//   C2C_TS_KIN:   x = in exp(-i qdt |mu|^2) / prod(N), the kinetic sub-step of the time splitting
+//                 (Sec. 4.1, Eq. tssp2).
+// alpha is read from device memory (the flow's stabilisation, computed on the device).
+struct GfLoad {
+  const void* aux = nullptr;
+  const double* alpha = nullptr;
+  double inv_dt = 0.0, inv_ntot = 0.0, qdt = 0.0;
+  double L[3] = {1.0, 1.0, 1.0};    // half-lengths L_i of the box
+  int n[3] = {1, 1, 1};
+};
 
 // The multiplier of the split's short-range part (Eq. 3.9) on the zero-padded grid, p = (1 - q) Uhat
 // at k_i = m_i dk[i], times scale:
@@ -46,7 +64,7 @@ hipError_t launch_strided(int n, Complex<T>* F, int axis, int d0, int d1, int d2
 template <typename T, int SIGN, int MODE>
 hipError_t launch_contig(int n, const void* in, void* out, int n0, int n1, int d0, int d1, int nc2, int z0, int nz,
                          const double* D0, const double* D1, const double* D2, const Complex<T>* tw,
-                         hipStream_t s);
+                         hipStream_t s, const GfLoad& gl = GfLoad{});
 
 // Lines along axis 0 of the [d0][d1][d2] padded spectrum of a real field, at last-axis
 // positions [0, nz) (the modes m2 in [0, nz), nz <= d2/2): transform the nc active inputs

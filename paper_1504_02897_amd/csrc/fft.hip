@@ -392,10 +392,11 @@ __global__ void __launch_bounds__(kContigThreads) k_fft_contig(const void* in, v
                                                     int n0, int n1, int d0, int d1, int nc2, int z0, int nz,
                                                     const double* __restrict__ D0, const double* __restrict__ D1,
                                                     const double* __restrict__ D2,
-                                                    const C<T>* __restrict__ tw, int B, int nlines) {
+                                                    const C<T>* __restrict__ tw, int B, int nlines, GfLoad gl) {
   extern __shared__ unsigned char smem_raw[];
   LdsElem<T, N>* lds = reinterpret_cast<LdsElem<T, N>*>(smem_raw);
   using P = Radix<T, N, true>;
+  constexpr bool kGf = MODE == C2C_GF_RES || MODE == C2C_GF_SOLVE || MODE == C2C_TS_KIN;
   constexpr int TL = N / P::R1;
   constexpr bool kWave = kContigWaveSync && 64 % TL == 0;   // every line inside one wave
   constexpr int LS = N + N / P::R1;      // padded line stride in LDS
@@ -436,6 +437,53 @@ __global__ void __launch_bounds__(kContigThreads) k_fft_contig(const void* in, v
         const int k = j0 + r * TL;
         v[r] = valid && active(k, N, nc2) ? C<T>{rho[rb + cmap(k, N, nc2)], T(0)} : C<T>{0, 0};
       }
+    } else if constexpr (kGf) {
+      const C<T>* F = reinterpret_cast<const C<T>*>(in);
+      const int64_t lbase = static_cast<int64_t>(valid ? line : 0) * N;
+      if constexpr (MODE == C2C_TS_KIN) {
+        const double pa = o0 < gl.n[0] / 2 ? o0 : o0 - gl.n[0];
+        const double pb = o1 < gl.n[1] / 2 ? o1 : o1 - gl.n[1];
+        const double ma = M_PI * pa / gl.L[0], mb = M_PI * pb / gl.L[1];
+        const double mab = (gl.n[0] > 1 ? ma * ma : 0.0) + mb * mb;
+#pragma unroll
+        for (int r = 0; r < P::R1; ++r) {
+          const int k = j0 + r * TL;
+          const double pc = k < N / 2 ? k : k - N;
+          const double mc = M_PI * pc / gl.L[2];
+          double sn, cs;
+          sincos(gl.qdt * (mab + mc * mc), &sn, &cs);   // exp(-i a) = cos a - i sin a
+          const C<T> x = F[lbase + k];
+          const double re = static_cast<double>(x.re), im = static_cast<double>(x.im);
+          v[r] = C<T>{static_cast<T>((re * cs + im * sn) * gl.inv_ntot), static_cast<T>((im * cs - re * sn) * gl.inv_ntot)};
+        }
+        return;
+      }
+      const double alpha = *gl.alpha;
+      if constexpr (MODE == C2C_GF_RES) {
+        const T* Bg = reinterpret_cast<const T*>(gl.aux);
+#pragma unroll
+        for (int r = 0; r < P::R1; ++r) {
+          const int k = j0 + r * TL;
+          const double f = alpha - static_cast<double>(Bg[lbase + k]);
+          const C<T> p = F[lbase + k];
+          v[r] = C<T>{static_cast<T>(f * p.re), static_cast<T>(f * p.im)};
+        }
+      } else {
+        const C<T>* R0 = reinterpret_cast<const C<T>*>(gl.aux);
+        const double pa = o0 < gl.n[0] / 2 ? o0 : o0 - gl.n[0];
+        const double pb = o1 < gl.n[1] / 2 ? o1 : o1 - gl.n[1];
+        const double ma = M_PI * pa / gl.L[0], mb = M_PI * pb / gl.L[1];
+        const double mab = (gl.n[0] > 1 ? ma * ma : 0.0) + mb * mb;
+#pragma unroll
+        for (int r = 0; r < P::R1; ++r) {
+          const int k = j0 + r * TL;
+          const double pc = k < N / 2 ? k : k - N;
+          const double mc = M_PI * pc / gl.L[2];
+          const double den = (gl.inv_dt + alpha + 0.5 * (mab + mc * mc)) / gl.inv_ntot;
+          const C<T> a = R0[lbase + k], b = F[lbase + k];
+          v[r] = C<T>{static_cast<T>((gl.inv_dt * a.re + b.re) / den), static_cast<T>((gl.inv_dt * a.im + b.im) / den)};
+        }
+      }
     } else {
       const C<T>* F = reinterpret_cast<const C<T>*>(in);
       int64_t lbase;
@@ -469,7 +517,7 @@ __global__ void __launch_bounds__(kContigThreads) k_fft_contig(const void* in, v
     } else {
       C<T>* F = reinterpret_cast<C<T>*>(out);
       int64_t lbase;
-      if (MODE == C2C) lbase = static_cast<int64_t>(line) * N;
+      if (MODE == C2C || kGf) lbase = static_cast<int64_t>(line) * N;
       else lbase = (static_cast<int64_t>(fmap(o0, d0, n0)) * d1 + fmap(o1, d1, n1)) * N;
 #pragma unroll
       for (int i = 0; i < P::R1; ++i) {
@@ -615,7 +663,12 @@ hipError_t launch_symbol(int n, C<T>* F, int d1, int d2, int nc, int nz, const S
 template <typename T, int N, int SIGN, int MODE>
 static hipError_t launch_contig_n(const void* in, void* out, int n0, int n1, int d0, int d1, int nc2, int z0,
                                   int nz, const double* D0, const double* D1, const double* D2, const C<T>* tw,
-                                  hipStream_t s) {
+                                  hipStream_t s, const GfLoad& gl) {
+  if ((MODE == C2C_GF_RES || MODE == C2C_GF_SOLVE) && (gl.aux == nullptr || gl.alpha == nullptr))
+    return hipErrorInvalidValue;
+  if ((MODE == C2C_GF_RES || MODE == C2C_GF_SOLVE || MODE == C2C_TS_KIN) &&
+      (z0 != 0 || nz != N || d0 != n0 || d1 != n1))
+    return hipErrorInvalidValue;
   if (z0 < 0 || z0 >= N || nz < 0 || nz > N) return hipErrorInvalidValue;
   constexpr int TL = N / Radix<T, N, true>::R1;
   constexpr int LS = N + N / Radix<T, N, true>::R1;
@@ -629,33 +682,33 @@ static hipError_t launch_contig_n(const void* in, void* out, int n0, int n1, int
                      : kContigBlocks > 0 ? std::min(ngroups, kContigBlocks) : ngroups;
   if (blocks < ngroups)
     hipLaunchKernelGGL((k_fft_contig<T, N, SIGN, MODE, true>), dim3(blocks), dim3(B * TL), shm, s, in, out, n0, n1,
-                       d0, d1, nc2, z0, nz, D0, D1, D2, tw, B, nlines);
+                       d0, d1, nc2, z0, nz, D0, D1, D2, tw, B, nlines, gl);
   else
     hipLaunchKernelGGL((k_fft_contig<T, N, SIGN, MODE, false>), dim3(blocks), dim3(B * TL), shm, s, in, out, n0, n1,
-                       d0, d1, nc2, z0, nz, D0, D1, D2, tw, B, nlines);
+                       d0, d1, nc2, z0, nz, D0, D1, D2, tw, B, nlines, gl);
   return hipGetLastError();
 }
 
 template <typename T, int SIGN, int MODE>
 hipError_t launch_contig(int n, const void* in, void* out, int n0, int n1, int d0, int d1, int nc2, int z0, int nz,
                                 const double* D0, const double* D1, const double* D2, const C<T>* tw,
-                                hipStream_t s) {
+                                hipStream_t s, const GfLoad& gl) {
   switch (n) {
-    case 8: return launch_contig_n<T, 8, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s);
-    case 16: return launch_contig_n<T, 16, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s);
-    case 32: return launch_contig_n<T, 32, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s);
-    case 64: return launch_contig_n<T, 64, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s);
-    case 128: return launch_contig_n<T, 128, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s);
-    case 256: return launch_contig_n<T, 256, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s);
-    case 512: return launch_contig_n<T, 512, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s);
-    case 1024: return launch_contig_n<T, 1024, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s);
-    case 12: return launch_contig_n<T, 12, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s);
-    case 24: return launch_contig_n<T, 24, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s);
-    case 48: return launch_contig_n<T, 48, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s);
-    case 96: return launch_contig_n<T, 96, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s);
-    case 192: return launch_contig_n<T, 192, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s);
-    case 384: return launch_contig_n<T, 384, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s);
-    case 768: return launch_contig_n<T, 768, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s);
+    case 8: return launch_contig_n<T, 8, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s, gl);
+    case 16: return launch_contig_n<T, 16, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s, gl);
+    case 32: return launch_contig_n<T, 32, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s, gl);
+    case 64: return launch_contig_n<T, 64, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s, gl);
+    case 128: return launch_contig_n<T, 128, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s, gl);
+    case 256: return launch_contig_n<T, 256, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s, gl);
+    case 512: return launch_contig_n<T, 512, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s, gl);
+    case 1024: return launch_contig_n<T, 1024, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s, gl);
+    case 12: return launch_contig_n<T, 12, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s, gl);
+    case 24: return launch_contig_n<T, 24, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s, gl);
+    case 48: return launch_contig_n<T, 48, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s, gl);
+    case 96: return launch_contig_n<T, 96, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s, gl);
+    case 192: return launch_contig_n<T, 192, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s, gl);
+    case 384: return launch_contig_n<T, 384, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s, gl);
+    case 768: return launch_contig_n<T, 768, SIGN, MODE>(in, out, n0, n1, d0, d1, nc2, z0, nz, D0, D1, D2, tw, s, gl);
     default: return hipErrorInvalidValue;
   }
 }
@@ -665,7 +718,8 @@ hipError_t launch_contig(int n, const void* in, void* out, int n0, int n1, int d
                                            const C<T>*, hipStream_t);
 #define DDI_INST_CONTIG(T, S, M)                                                                                \
   template hipError_t launch_contig<T, S, M>(int, const void*, void*, int, int, int, int, int, int, int,        \
-                                             const double*, const double*, const double*, const C<T>*, hipStream_t);
+                                             const double*, const double*, const double*, const C<T>*, hipStream_t, \
+                                             const GfLoad&);
 DDI_INST_STRIDED(double, 1)
 DDI_INST_STRIDED(double, -1)
 DDI_INST_STRIDED(float, 1)
@@ -684,6 +738,12 @@ DDI_INST_CONTIG(float, 1, C2R_TRUNC)
 DDI_INST_CONTIG(float, -1, C2R_TRUNC)
 DDI_INST_CONTIG(double, 1, C2R_ADD)
 DDI_INST_CONTIG(float, 1, C2R_ADD)
+DDI_INST_CONTIG(double, -1, C2C_GF_RES)
+DDI_INST_CONTIG(float, -1, C2C_GF_RES)
+DDI_INST_CONTIG(double, 1, C2C_GF_SOLVE)
+DDI_INST_CONTIG(float, 1, C2C_GF_SOLVE)
+DDI_INST_CONTIG(double, 1, C2C_TS_KIN)
+DDI_INST_CONTIG(float, 1, C2C_TS_KIN)
 template hipError_t launch_symbol<double>(int, C<double>*, int, int, int, int, const SplitSymbol&, const C<double>*,
                                           hipStream_t);
 template hipError_t launch_symbol<float>(int, C<float>*, int, int, int, int, const SplitSymbol&, const C<float>*,

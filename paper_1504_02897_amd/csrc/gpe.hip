@@ -49,6 +49,12 @@ __device__ __forceinline__ double mu2_of(int64_t i, const GridGeo& G) {
 }
 
 constexpr int kRedThreads = 256;
+#ifndef DDI_GF_FUSED
+#define DDI_GF_FUSED 1
+#endif
+// the gradient-flow step's residual and solve, and the time splitting's kinetic factor, folded
+// into the first passes of their transforms
+constexpr bool kGfFused = DDI_GF_FUSED != 0;
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_density(const C<T>* __restrict__ psi, T* __restrict__ rho, int64_t n) {
@@ -359,13 +365,14 @@ int gpe_reduction_blocks(const DevicePlan& P) {
 
 // Complex 3D FFT of an unpadded N0 x N1 x N2 grid into X, in place, or from `in` when it is
 // given (the first pass reads it; `in` is not modified).
-template <typename T, int SIGN>
-static hipError_t fft3_full(DevicePlan& P, C<T>* X, hipStream_t s, const C<T>* in = nullptr) {
+template <typename T, int SIGN, int MODE0 = C2C>
+static hipError_t fft3_full(DevicePlan& P, C<T>* X, hipStream_t s, const C<T>* in = nullptr,
+                            const GfLoad& gl = GfLoad{}) {
   const HostTables& H = P.H;
   const C<T>* tw2 = reinterpret_cast<const C<T>*>(P.twiddles[tw_slot(H.N[2])]);
   const C<T>* src = in ? in : X;
-  DDI_CHECK((launch_contig<T, SIGN, C2C>(H.N[2], src, X, H.N[0], H.N[1], H.N[0], H.N[1], H.N[2], 0, H.N[2], nullptr,
-                                         nullptr, nullptr, tw2, s)));
+  DDI_CHECK((launch_contig<T, SIGN, MODE0>(H.N[2], src, X, H.N[0], H.N[1], H.N[0], H.N[1], H.N[2], 0, H.N[2],
+                                           nullptr, nullptr, nullptr, tw2, s, gl)));
   DDI_CHECK((launch_strided<T, SIGN>(H.N[1], X, 1, H.N[0], H.N[1], H.N[2], H.N[0], 0, H.N[1], 0, 0, H.N[1], 0, H.N[2],
                                      reinterpret_cast<const C<T>*>(P.twiddles[tw_slot(H.N[1])]), s)));
   if (H.N[0] > 1) {
@@ -442,15 +449,30 @@ hipError_t run_gf_step(DevicePlan& P, const gpe_params& gp, double dt, int n_inn
   DDI_CHECK(hipGetLastError());
   // rhs0 = FFT(psi_in); k_gf_solve divides it by dt
   DDI_CHECK((fft3_full<T, -1>(P, rhs0, s, psi_in)));
-  // the iterate: psi_in, then r (updated in place); normalised into psi_out at the end
+  // the iterate: psi_in, then r (updated in place); normalised into psi_out at the end.  The
+  // residual (alpha - B) cur is formed in the loads of the forward transform's first pass, and
+  // the Fourier-space solve in the loads of the inverse transform's first pass.
+  GfLoad gl;
+  gl.alpha = scal;
+  gl.inv_dt = 1.0 / dt;
+  gl.inv_ntot = inv_ntot;
+  gl.L[0] = G.L0; gl.L[1] = G.L1; gl.L[2] = G.L2;
+  gl.n[0] = G.N0; gl.n[1] = G.N1; gl.n[2] = G.N2;
   const Complex<T>* cur = psi_in;
   for (int it = 0; it < n_inner; ++it) {
-    hipLaunchKernelGGL((k_gf_residual<T>), dim3(ew_blocks(n)), dim3(256), 0, s, cur, Bc, scal, n, r);
-    DDI_CHECK(hipGetLastError());
-    DDI_CHECK((fft3_full<T, -1>(P, r, s)));
-    hipLaunchKernelGGL((k_gf_solve<T>), dim3(ew_blocks(n)), dim3(256), 0, s, r, rhs0, scal, n, G, dt, inv_ntot);
-    DDI_CHECK(hipGetLastError());
-    DDI_CHECK((fft3_full<T, +1>(P, r, s)));
+    if (kGfFused) {
+      gl.aux = Bc;
+      DDI_CHECK((fft3_full<T, -1, C2C_GF_RES>(P, r, s, cur, gl)));
+      gl.aux = rhs0;
+      DDI_CHECK((fft3_full<T, +1, C2C_GF_SOLVE>(P, r, s, nullptr, gl)));
+    } else {
+      hipLaunchKernelGGL((k_gf_residual<T>), dim3(ew_blocks(n)), dim3(256), 0, s, cur, Bc, scal, n, r);
+      DDI_CHECK(hipGetLastError());
+      DDI_CHECK((fft3_full<T, -1>(P, r, s)));
+      hipLaunchKernelGGL((k_gf_solve<T>), dim3(ew_blocks(n)), dim3(256), 0, s, r, rhs0, scal, n, G, dt, inv_ntot);
+      DDI_CHECK(hipGetLastError());
+      DDI_CHECK((fft3_full<T, +1>(P, r, s)));
+    }
     cur = r;
   }
   hipLaunchKernelGGL((k_norm2<T>), dim3(nb), dim3(kRedThreads), 0, s, cur, n, red);
@@ -490,6 +512,14 @@ hipError_t run_ts_step(DevicePlan& P, const gpe_params& gp, double dt, double de
   // the first transform reads psi_in; everything after it works in place on psi_out
   auto half_kinetic = [&](const Complex<T>* from) -> hipError_t {
     DDI_CHECK((fft3_full<T, -1>(P, psi_out, s, from)));
+    if (kGfFused) {   // the kinetic factor in the loads of the inverse transform's first pass
+      GfLoad gl;
+      gl.qdt = 0.25 * dt;
+      gl.inv_ntot = inv_ntot;
+      gl.L[0] = G.L0; gl.L[1] = G.L1; gl.L[2] = G.L2;
+      gl.n[0] = G.N0; gl.n[1] = G.N1; gl.n[2] = G.N2;
+      return fft3_full<T, +1, C2C_TS_KIN>(P, psi_out, s, nullptr, gl);
+    }
     hipLaunchKernelGGL((k_ts_kinetic<T>), dim3(ew_blocks(n)), dim3(256), 0, s, psi_out, n, G, 0.25 * dt, inv_ntot);
     DDI_CHECK(hipGetLastError());
     return fft3_full<T, +1>(P, psi_out, s);
