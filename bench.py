@@ -69,7 +69,7 @@ def stage_model(plan, real_bytes, cplx_bytes):
 KERNELS = {"fft_last_pad": "k_fft_contig (R2C_PAD)", "fft_axis1_t2": "k_fft_strided (axis 1)",
            "fft_axis0_t2": "k_fft_strided (axis 0)",
            "interp": "k_interp_mfma + k_interp_gather (FP64, 3D); k_interp_lds + k_interp (FP32, 2D)",
-           "spread": "k_spread_mfma (3D); k_spread (2D)", "spread_reduce": "k_spread_reduce", "fft_axis0_t1": "k_fft_strided (axis 0)",
+           "spread": "k_spread_mfma (3D); k_spread2d (2D)", "spread_reduce": "k_spread_reduce", "fft_axis0_t1": "k_fft_strided (axis 0)",
            "fft_axis1_t1": "k_fft_strided (axis 1)", "fft_last_trunc": "k_fft_contig (C2R_TRUNC)"}
 
 
